@@ -1,0 +1,102 @@
+"""Matrix-free FP64 apply of A and A^T (oracle; test infrastructure only).
+
+Same rows as ``assemble`` (the real P_N equations discretised by central
+differences on the staggered grid), evaluated with whole-array NumPy slices so
+that grids too large for an assembled matrix can be checked.  ``A^T`` is the
+literal transpose: every entry (row, col, v) of A is scattered as (col, row, v).
+It does not use the skew symmetry of the transport part; ``tests/`` checks
+that property separately.
+
+``tests/`` pins both functions to the CSR matrix of ``assemble`` on small grids.
+"""
+import numpy as np
+
+from .couplings import coupling_list
+from .medium import diagonal
+from .stagger import Layout, BC_PERIODIC
+
+_AXIS = (2, 1, 0)  # x, y, z -> axis of an (ez, ey, ex) array
+
+
+def _gather(arr, d, offset, out_len, bc):
+    """b[i] = arr[i + offset] along axis d for i < out_len; 0 outside (vacuum)
+    or wrapped (periodic)."""
+    ax = _AXIS[d]
+    n = arr.shape[ax]
+    idx = np.arange(out_len) + offset
+    if bc == BC_PERIODIC:
+        return np.take(arr, np.mod(idx, n), axis=ax)
+    keep = (idx >= 0) & (idx < n)
+    shape = list(arr.shape)
+    shape[ax] = out_len
+    out = np.zeros(shape)
+    sl_out = [slice(None)] * 3
+    sl_out[ax] = np.nonzero(keep)[0]
+    out[tuple(sl_out)] = np.take(arr, idx[keep], axis=ax)
+    return out
+
+
+def _scatter_add(dst, src, d, offset, bc):
+    """dst[i + offset] += src[i] along axis d (dropped outside unless periodic)."""
+    ax = _AXIS[d]
+    n = dst.shape[ax]
+    idx = np.arange(src.shape[ax]) + offset
+    if bc == BC_PERIODIC:
+        idx = np.mod(idx, n)
+        keep = np.ones(idx.shape, dtype=bool)
+    else:
+        keep = (idx >= 0) & (idx < n)
+    for j in np.nonzero(keep)[0]:
+        sl_d = [slice(None)] * 3
+        sl_s = [slice(None)] * 3
+        sl_d[ax] = idx[j]
+        sl_s[ax] = j
+        dst[tuple(sl_d)] += src[tuple(sl_s)]
+
+
+class Operator:
+    """FP64 matrix-free operator of one medium."""
+
+    def __init__(self, order, dims, sigma_t, albedo, g, sigma_t_min, bc=0, couplings=None):
+        self.layout = Layout(order, dims, bc)
+        self.couplings = coupling_list(order) if couplings is None else couplings
+        self.diag = diagonal(self.layout, sigma_t, albedo, g, sigma_t_min)
+        self.h = 1.0 / dims[0]
+        self.bc = bc
+
+    @property
+    def n(self):
+        return self.layout.n
+
+    def matvec(self, x):
+        lay = self.layout
+        x = np.asarray(x, dtype=np.float64)
+        y = np.zeros(lay.n)
+        for k in range(lay.ncoeff):
+            lay.view(y, k)[...] = self.diag[k] * lay.view(x, k)
+        for (k, d, kp, c) in self.couplings:
+            xk = lay.view(x, kp)
+            out_len = lay.ext[k][d]
+            if lay.cls[kp][d] == 1:
+                plus, minus = _gather(xk, d, 1, out_len, self.bc), _gather(xk, d, 0, out_len, self.bc)
+            else:
+                plus, minus = _gather(xk, d, 0, out_len, self.bc), _gather(xk, d, -1, out_len, self.bc)
+            lay.view(y, k)[...] += (c / self.h) * (plus - minus)
+        return y
+
+    def rmatvec(self, x):
+        lay = self.layout
+        x = np.asarray(x, dtype=np.float64)
+        y = np.zeros(lay.n)
+        for k in range(lay.ncoeff):
+            lay.view(y, k)[...] = self.diag[k] * lay.view(x, k)
+        for (k, d, kp, c) in self.couplings:
+            src = (c / self.h) * lay.view(x, k)
+            dst = lay.view(y, kp)
+            if lay.cls[kp][d] == 1:
+                _scatter_add(dst, src, d, 1, self.bc)
+                _scatter_add(dst, -src, d, 0, self.bc)
+            else:
+                _scatter_add(dst, src, d, 0, self.bc)
+                _scatter_add(dst, -src, d, -1, self.bc)
+        return y
