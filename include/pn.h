@@ -1,0 +1,176 @@
+/*
+ * pn.h -- C ABI of the MI355X (gfx950) staggered-grid real P_N solver.
+ *
+ * Method: Koerner, Portsmouth & Jakob, "P_N-Method for Multiple Scattering in
+ * Participating Media" (EGSR 2018).  The radiative transfer equation is
+ * projected onto real spherical harmonics up to order N ((N+1)^2 coefficients
+ * L^{l,m}, section "Real-valued P_N-Equations"), discretised by central
+ * differences on a staggered voxel grid (section "Precomputation") and the
+ * resulting sparse system A u = Q (section "Discretized Radiative Transfer
+ * Equation", A = T + C - S) is solved iteratively on the normal equations
+ * A^T A u = A^T Q (section "Runtime").
+ *
+ * Conventions common to every entry point
+ *  - All array pointers are DEVICE pointers (HIP device memory of the current
+ *    device) unless stated otherwise.  The caller owns them; the library never
+ *    frees them.  The library owns its context and workspace (pn_destroy).
+ *  - Cell-centred fields are nz*ny*nx arrays, x fastest, z slowest.
+ *  - Solution / right-hand-side vectors use the "staggered SoA" layout reported
+ *    by pn_layout_query: coefficient k = l*l + l + m occupies the contiguous
+ *    range [offset[k], offset[k+1]) and is itself an (ez, ey, ex) array (x
+ *    fastest) over the lattice of its staggering class (cls[k] = (px,py,pz)).
+ *    A class with p_d = 1 sits on the cell faces normal to axis d; under the
+ *    vacuum boundary its extent along d is n_d + 1 (both boundary faces), under
+ *    the periodic boundary it is n_d.  Classes follow the reflection parities
+ *    of Y_R^{l,m}: px = m mod 2 (m >= 0) or (|m|+1) mod 2 (m < 0),
+ *    py = [m < 0], pz = (l + |m|) mod 2.
+ *  - Errors are reported by status code, never by exception or abort.
+ *    pn_last_error(ctx) returns a message for the last failing call on ctx.
+ *  - A context is bound to one HIP stream (given at setup).  pn_apply and
+ *    pn_apply64 are asynchronous on that stream; pn_solve and pn_residual64
+ *    return after the result is complete (they synchronise with the host).
+ *  - Calls on one context must not overlap (contexts are not thread-safe).
+ */
+#ifndef PN_H
+#define PN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PN_ABI_VERSION 1
+#define PN_MAX_ORDER 7
+#define PN_MAX_COEFF 64
+
+typedef struct pn_ctx pn_ctx;
+
+typedef enum {
+  PN_OK = 0,
+  PN_ERR_ARG = 1,            /* invalid argument (null pointer, order, size)  */
+  PN_ERR_ALLOC = 2,          /* device or host allocation failed              */
+  PN_ERR_HIP = 3,            /* a HIP runtime call failed                     */
+  PN_ERR_NONFINITE = 4,      /* NaN/Inf in the medium or the right-hand side  */
+  PN_ERR_NOT_CONVERGED = 5,  /* tolerance not reached within the limits       */
+  PN_ERR_BREAKDOWN = 6       /* Krylov breakdown (zero curvature)             */
+} pn_status;
+
+typedef enum { PN_BC_VACUUM = 0, PN_BC_PERIODIC = 1 } pn_bc;
+typedef enum { PN_FP32_IR = 0, PN_FP64 = 1 } pn_precision;
+
+/* Grid of nx*ny*nz cells of edge h (h <= 0 selects h = 1/nx, i.e. the unit
+ * cube for cubic grids).  bc: PN_BC_VACUUM = homogeneous Dirichlet on every
+ * coefficient (the paper's Dirichlet mode: writes to locations outside the
+ * domain are dropped, section "Runtime"), PN_BC_PERIODIC = wrap-around. */
+typedef struct {
+  int nx, ny, nz;
+  double h;
+  int bc;
+} pn_grid;
+
+/* RTE parameters at the cell centres (section "Runtime": "RTE parameter
+ * fields").  sigma_t: extinction; albedo: sigma_s / sigma_t; g: the
+ * Henyey-Greenstein mean cosine, uniform over the medium (the phase-function
+ * moments enter as lambda_l p^{l,0} = g^l, appendix "Scattering term");
+ * sigma_t_min: every cell with sigma_t < sigma_t_min is raised to it (the
+ * paper's extinction threshold; vacuum makes A singular).  sigma_s is
+ * albedo * thresholded sigma_t.  Both arrays are device FP32, nz*ny*nx.  The
+ * library copies what it needs at setup; the caller may free them after. */
+typedef struct {
+  const float* sigma_t;
+  const float* albedo;
+  float g;
+  float sigma_t_min;
+} pn_medium;
+
+typedef struct {
+  int order, ncoeff;
+  int nx, ny, nz, bc;
+  long long n_unknowns;
+  int cls[PN_MAX_COEFF][3];
+  int ext[PN_MAX_COEFF][3];          /* (ex, ey, ez) per coefficient          */
+  long long offset[PN_MAX_COEFF + 1];
+} pn_layout;
+
+typedef struct {
+  int precision;      /* PN_FP32_IR (FP32 Krylov + FP64 refinement) or PN_FP64 */
+  int max_iter;       /* total Krylov iterations over all refinement steps    */
+  int max_refine;     /* refinement steps (PN_FP32_IR)                         */
+  double inner_tol;   /* relative reduction of the inner FP32 residual         */
+  int use_guess;      /* 0: start from x = 0; 1: start from the x passed in    */
+  int graph_iters;    /* Krylov iterations per captured HIP graph launch       */
+} pn_solve_opts;
+
+#define PN_MAX_HISTORY 64
+typedef struct {
+  int status;
+  int outer_iters;          /* FP64 residual evaluations                       */
+  int inner_iters;          /* Krylov iterations (each = one A and one A^T)    */
+  double rel_residual;      /* ||Q - A x||_2 / ||Q||_2 in FP64 at exit         */
+  double bnorm;             /* ||Q||_2                                         */
+  double seconds;           /* wall time of the solve                          */
+  int nhistory;
+  double history[PN_MAX_HISTORY]; /* FP64 relative residual per refinement step */
+} pn_solve_info;
+
+int pn_abi_version(void);
+const char* pn_status_string(int status);
+
+/* Default options: FP32_IR, max_iter 200000, max_refine 40, inner_tol 1e-3,
+ * use_guess 0, graph_iters 32. */
+void pn_default_opts(pn_solve_opts* opts);
+
+/* Builds a solver context for truncation order 1 <= order <= 7 on `grid`
+ * with `medium` (section "Runtime": the system is built from the RTE
+ * parameter fields, the resolution and the boundary type).  The
+ * transport couplings int omega_d Y^k Y^k' are the closed forms of the
+ * appendix ("Final equation", real-valued derivation).  Thresholds sigma_t,
+ * checks the medium for NaN/Inf (PN_ERR_NONFINITE) and allocates the Krylov
+ * workspace (5 FP32 vectors).  `stream` is a hipStream_t (NULL = the null
+ * stream).  On failure *out is NULL. */
+pn_status pn_setup(int order, const pn_grid* grid, const pn_medium* medium,
+                   void* stream, pn_ctx** out);
+
+/* Fills *layout (host struct) with the staggered SoA layout of ctx. */
+pn_status pn_layout_query(const pn_ctx* ctx, pn_layout* layout);
+
+/* y = A x (transpose == 0) or y = A^T x (transpose != 0) in FP32, where A is
+ * the discretised operator of section "Discretized Radiative Transfer
+ * Equation": per row of coefficient k (band l) at lattice point x_i,
+ *   sum_d sum_k' A_d[k,k'] (x_k'(x_i + h/2 e_d) - x_k'(x_i - h/2 e_d)) / h
+ *   + (sigma_t(x_i) - g^l sigma_s(x_i)) x_k(x_i)
+ * with sigma_t, sigma_s averaged from the adjacent cell centres.  A^T flips
+ * the sign of the transport part (it is skew-symmetric).  x and y are device
+ * FP32 vectors of n_unknowns entries and must not overlap.  Asynchronous. */
+pn_status pn_apply(pn_ctx* ctx, const float* x, float* y, int transpose);
+
+/* Same operator evaluated in FP64 (couplings, interpolation and products in
+ * double) on FP64 vectors.  Asynchronous. */
+pn_status pn_apply64(pn_ctx* ctx, const double* x, double* y, int transpose);
+
+/* r = Q - A x in FP64 (x FP64, Q FP32, r FP64 output, may be NULL) and the
+ * relative residual ||r||_2 / ||Q||_2 written to *rel (host).  Synchronous. */
+pn_status pn_residual64(pn_ctx* ctx, const float* rhs, const double* x,
+                        double* r, double* rel);
+
+/* Solves A x = Q (rhs = Q, device FP32; x device FP64, in/out) to
+ * ||Q - A x||_2 <= tol ||Q||_2 with the residual evaluated in FP64.
+ * PN_FP32_IR: iterative refinement around CGLS (conjugate gradients on the
+ * normal equations without forming A^T A, section "Runtime" / "Results") run
+ * in FP32 with FP64 dot products and scalars.  PN_FP64: CGLS in FP64
+ * throughout.  Returns PN_ERR_NOT_CONVERGED (x = last iterate, finite) when
+ * the limits are hit, PN_ERR_NONFINITE for a non-finite rhs.  rhs == 0
+ * returns x = 0 immediately.  opts NULL = defaults; info may be NULL. */
+pn_status pn_solve(pn_ctx* ctx, const float* rhs, double* x, double tol,
+                   const pn_solve_opts* opts, pn_solve_info* info);
+
+/* Frees the context and its workspace.  NULL is ignored. */
+void pn_destroy(pn_ctx* ctx);
+
+/* Message of the last failing call on ctx (or of the last failing pn_setup
+ * when ctx is NULL).  The string is owned by the library. */
+const char* pn_last_error(const pn_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PN_H */

@@ -100,3 +100,64 @@ class Operator:
                 _scatter_add(dst, src, d, 0, self.bc)
                 _scatter_add(dst, -src, d, -1, self.bc)
         return y
+
+
+def rows_of(order, dims, sigma_t, albedo, g, sigma_t_min, x, rows, bc=0, couplings=None, absolute=False):
+    """(A x)[row] for the given flat row indices, evaluated one row at a time
+    from the row equation (no assembled matrix, no whole-grid arrays).  For
+    spot checks of grids too large for ``Operator``.  With ``absolute=True``
+    returns (|A| |x|)[row] instead (the sum of the magnitudes of the terms),
+    the scale of a rounding-error bound."""
+    ab = abs if absolute else (lambda v: v)
+    from .stagger import Layout
+    from .sh import coeff_lm
+    lay = Layout(order, dims, bc)
+    cl = coupling_list(order) if couplings is None else couplings
+    by_row = {}
+    for (k, d, kp, c) in cl:
+        by_row.setdefault(k, []).append((d, kp, c))
+    st = np.maximum(np.asarray(sigma_t, dtype=np.float64), float(np.float32(sigma_t_min)))
+    ss = np.asarray(albedo, dtype=np.float64) * st
+    n = (dims[0], dims[1], dims[2])
+    h = 1.0 / dims[0]
+    g = float(np.float32(g))
+    x = np.asarray(x)
+    out = np.empty(len(rows))
+    for t, row in enumerate(rows):
+        k = int(np.searchsorted(lay.offset, row, side="right") - 1)
+        ex, ey, ez = lay.ext[k]
+        loc = int(row - lay.offset[k])
+        pt = [loc % ex, (loc // ex) % ey, loc // (ex * ey)]
+        p = lay.cls[k]
+        # parameters: mean over the adjacent cells (clamped or wrapped), z-major order
+        cand = []
+        for d in range(3):
+            cs = [pt[d]] if p[d] == 0 else [pt[d] - 1, pt[d]]
+            cand.append([(c % n[d]) if bc == BC_PERIODIC else min(max(c, 0), n[d] - 1) for c in cs])
+        tsum, ssum, cnt = 0.0, 0.0, 0
+        for cz in cand[2]:
+            for cy in cand[1]:
+                for cx in cand[0]:
+                    tsum += st[cz, cy, cx]
+                    ssum += ss[cz, cy, cx]
+                    cnt += 1
+        l = coeff_lm(k)[0]
+        if absolute:  # magnitudes before the sigma_t - g^l sigma_s cancellation
+            val = (tsum / cnt + (abs(float(g)) ** l) * (ssum / cnt)) * abs(float(x[row]))
+        else:
+            val = (tsum / cnt - (float(g) ** l) * (ssum / cnt)) * float(x[row])
+        for (d, kp, c) in by_row.get(k, []):
+            pe = lay.ext[kp]
+            i = pt[d]
+            ip, im = (i + 1, i) if lay.cls[kp][d] == 1 else (i, i - 1)
+            for idx, sgn in ((ip, 1.0), (im, -1.0)):
+                if bc == BC_PERIODIC:
+                    idx %= pe[d]
+                elif not (0 <= idx < pe[d]):
+                    continue
+                q = list(pt)
+                q[d] = idx
+                col = lay.offset[kp] + (q[2] * pe[1] + q[1]) * pe[0] + q[0]
+                val += ab(sgn * c / h * float(x[col]))
+        out[t] = val
+    return out

@@ -13,7 +13,8 @@
   Henyey-Greenstein phase function lambda_l p^{l,0} = g^l (pinned in
   ``couplings.scattering_factors``).
 
-All arithmetic is FP64; the inputs are FP32 arrays (exactly representable).
+All arithmetic is FP64; the inputs (fields, g, sigma_t_min) are FP32 values,
+rounded once from whatever the caller passes.
 """
 import numpy as np
 
@@ -22,8 +23,9 @@ from .stagger import BC_PERIODIC
 
 
 def threshold(sigma_t, sigma_t_min):
-    """max(sigma_t, sigma_t_min) cell by cell, in FP64."""
-    return np.maximum(np.asarray(sigma_t, dtype=np.float64), float(sigma_t_min))
+    """max(sigma_t, sigma_t_min) cell by cell, in FP64.  The threshold is an
+    FP32 input like the fields, so it is rounded to FP32 first."""
+    return np.maximum(np.asarray(sigma_t, dtype=np.float64), float(np.float32(sigma_t_min)))
 
 
 def interpolate_to_class(field, p, ext, bc):
@@ -67,6 +69,7 @@ def diagonal(layout, sigma_t, albedo, g, sigma_t_min):
     """
     st = threshold(sigma_t, sigma_t_min)
     ss = np.asarray(albedo, dtype=np.float64) * st
+    g = float(np.float32(g))  # an FP32 input, like the fields
     cache = {}
     out = []
     for k in range(layout.ncoeff):

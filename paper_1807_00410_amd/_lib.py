@@ -1,0 +1,90 @@
+"""ctypes declarations of the C ABI in include/pn.h (argument marshalling only)."""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpn.so")
+
+PN_MAX_COEFF = 64
+PN_MAX_HISTORY = 64
+
+PN_OK = 0
+PN_ERR_ARG = 1
+PN_ERR_ALLOC = 2
+PN_ERR_HIP = 3
+PN_ERR_NONFINITE = 4
+PN_ERR_NOT_CONVERGED = 5
+PN_ERR_BREAKDOWN = 6
+
+PN_BC_VACUUM = 0
+PN_BC_PERIODIC = 1
+PN_FP32_IR = 0
+PN_FP64 = 1
+
+
+class PnGrid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double), ("bc", C.c_int)]
+
+
+class PnMedium(C.Structure):
+    _fields_ = [("sigma_t", C.c_void_p), ("albedo", C.c_void_p), ("g", C.c_float), ("sigma_t_min", C.c_float)]
+
+
+class PnLayout(C.Structure):
+    _fields_ = [("order", C.c_int), ("ncoeff", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("bc", C.c_int), ("n_unknowns", C.c_longlong),
+                ("cls", (C.c_int * 3) * PN_MAX_COEFF), ("ext", (C.c_int * 3) * PN_MAX_COEFF),
+                ("offset", C.c_longlong * (PN_MAX_COEFF + 1))]
+
+
+class PnSolveOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("max_iter", C.c_int), ("max_refine", C.c_int),
+                ("inner_tol", C.c_double), ("use_guess", C.c_int), ("graph_iters", C.c_int)]
+
+
+class PnSolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("outer_iters", C.c_int), ("inner_iters", C.c_int),
+                ("rel_residual", C.c_double), ("bnorm", C.c_double), ("seconds", C.c_double),
+                ("nhistory", C.c_int), ("history", C.c_double * PN_MAX_HISTORY)]
+
+
+# (name, restype, argtypes) of every exported symbol declared in include/pn.h
+SIGNATURES = [
+    ("pn_abi_version", C.c_int, []),
+    ("pn_status_string", C.c_char_p, [C.c_int]),
+    ("pn_default_opts", None, [C.POINTER(PnSolveOpts)]),
+    ("pn_setup", C.c_int, [C.c_int, C.POINTER(PnGrid), C.POINTER(PnMedium), C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("pn_layout_query", C.c_int, [C.c_void_p, C.POINTER(PnLayout)]),
+    ("pn_apply", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    ("pn_apply64", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    ("pn_residual64", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    ("pn_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.POINTER(PnSolveOpts),
+                           C.POINTER(PnSolveInfo)]),
+    ("pn_destroy", None, [C.c_void_p]),
+    ("pn_last_error", C.c_char_p, [C.c_void_p]),
+    ("pn_set_zchunk", C.c_int, [C.c_void_p, C.c_int]),
+    ("pn_get_zchunk", C.c_int, [C.c_void_p]),
+    ("pn_coupling_table", C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                    C.POINTER(C.c_double), C.c_int]),
+]
+
+_lib = None
+
+
+def load(path=None):
+    """Loads libpn.so (built by paper_1807_00410_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError("libpn.so not found at %s: run `python -m paper_1807_00410_amd.build` "
+                           "(there is no CPU fallback)" % p)
+    lib = C.CDLL(p)
+    for name, res, args in SIGNATURES:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib

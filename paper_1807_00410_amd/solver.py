@@ -1,0 +1,158 @@
+"""Python handle around the C ABI (include/pn.h).  Marshals torch device
+tensors into pointers; every step of the solve runs in the HIP library."""
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+
+class PnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (status %d): %s" % (L.load().pn_status_string(status).decode(), status, msg))
+        self.status = status
+
+
+def _ptr(t, dtype):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != dtype:
+        raise TypeError("expected %s, got %s" % (dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Layout:
+    """Staggered SoA layout reported by pn_layout_query."""
+
+    def __init__(self, raw):
+        self.order = raw.order
+        self.ncoeff = raw.ncoeff
+        self.dims = (raw.nx, raw.ny, raw.nz)
+        self.bc = raw.bc
+        self.n = int(raw.n_unknowns)
+        self.cls = [tuple(raw.cls[k]) for k in range(self.ncoeff)]
+        self.ext = [tuple(raw.ext[k]) for k in range(self.ncoeff)]
+        self.offset = [int(raw.offset[k]) for k in range(self.ncoeff + 1)]
+
+    def view(self, vec, k):
+        ex, ey, ez = self.ext[k]
+        return vec[self.offset[k]:self.offset[k + 1]].view(ez, ey, ex)
+
+
+class Solver:
+    """One medium on one grid: pn_setup ... pn_destroy."""
+
+    def __init__(self, order, dims, sigma_t, albedo, g=0.0, sigma_t_min=0.0, bc=L.PN_BC_VACUUM, h=0.0,
+                 stream=None):
+        self.lib = L.load()
+        st = sigma_t.contiguous()
+        al = albedo.contiguous()
+        grid = L.PnGrid(int(dims[0]), int(dims[1]), int(dims[2]), float(h), int(bc))
+        med = L.PnMedium(_ptr(st, torch.float32), _ptr(al, torch.float32), float(g), float(sigma_t_min))
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        ctx = C.c_void_p()
+        rc = self.lib.pn_setup(int(order), C.byref(grid), C.byref(med), C.c_void_p(s.cuda_stream), C.byref(ctx))
+        if rc != L.PN_OK:
+            raise PnError(rc, self.lib.pn_last_error(None).decode())
+        self.ctx = ctx
+        raw = L.PnLayout()
+        self._check(self.lib.pn_layout_query(self.ctx, C.byref(raw)))
+        self.layout = Layout(raw)
+
+    def _check(self, rc):
+        if rc != L.PN_OK:
+            raise PnError(rc, self.lib.pn_last_error(self.ctx).decode())
+
+    @property
+    def n(self):
+        return self.layout.n
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.pn_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------ kernels --
+    def apply(self, x, y=None, transpose=False):
+        y = torch.empty_like(x) if y is None else y
+        self._check(self.lib.pn_apply(self.ctx, _ptr(x, torch.float32), _ptr(y, torch.float32), int(transpose)))
+        return y
+
+    def apply64(self, x, y=None, transpose=False):
+        y = torch.empty_like(x) if y is None else y
+        self._check(self.lib.pn_apply64(self.ctx, _ptr(x, torch.float64), _ptr(y, torch.float64), int(transpose)))
+        return y
+
+    def residual64(self, rhs, x, r=None):
+        rel = C.c_double()
+        self._check(self.lib.pn_residual64(self.ctx, _ptr(rhs, torch.float32), _ptr(x, torch.float64),
+                                           _ptr(r, torch.float64) if r is not None else None, C.byref(rel)))
+        return rel.value
+
+    def set_zchunk(self, z):
+        self._check(self.lib.pn_set_zchunk(self.ctx, int(z)))
+
+    def zchunk(self):
+        return self.lib.pn_get_zchunk(self.ctx)
+
+    def solve(self, rhs, x=None, tol=1e-8, precision="fp32_ir", max_iter=200000, max_refine=40,
+              inner_tol=1e-3, use_guess=False, graph_iters=32, raise_on_fail=True):
+        """Solves A x = rhs.  Returns (x, info dict)."""
+        if x is None:
+            x = torch.zeros(self.n, dtype=torch.float64, device=rhs.device)
+        opts = L.PnSolveOpts()
+        self.lib.pn_default_opts(C.byref(opts))
+        opts.precision = L.PN_FP64 if precision == "fp64" else L.PN_FP32_IR
+        opts.max_iter = int(max_iter)
+        opts.max_refine = int(max_refine)
+        opts.inner_tol = float(inner_tol)
+        opts.use_guess = int(bool(use_guess))
+        opts.graph_iters = int(graph_iters)
+        info = L.PnSolveInfo()
+        rc = self.lib.pn_solve(self.ctx, _ptr(rhs, torch.float32), _ptr(x, torch.float64), float(tol),
+                               C.byref(opts), C.byref(info))
+        d = dict(status=rc, outer_iters=info.outer_iters, inner_iters=info.inner_iters,
+                 rel_residual=info.rel_residual, bnorm=info.bnorm, seconds=info.seconds,
+                 history=[info.history[i] for i in range(info.nhistory)])
+        if rc != L.PN_OK and raise_on_fail:
+            raise PnError(rc, self.lib.pn_last_error(self.ctx).decode())
+        return x, d
+
+    # ---------------------------------------------------------- marshalling --
+    def rhs_from_q00(self, q00):
+        """Right-hand side vector for an isotropic emission Q^{00} per cell
+        (coefficient 0 sits at the cell centres; all other entries zero)."""
+        rhs = torch.zeros(self.n, dtype=torch.float32, device=q00.device)
+        rhs[self.layout.offset[0]:self.layout.offset[1]] = q00.reshape(-1).to(torch.float32)
+        return rhs
+
+
+def coupling_table(order):
+    """(k, d, k', value) list compiled into the library for `order`."""
+    lib = L.load()
+    cap = 1024
+    k = (C.c_int * cap)()
+    d = (C.c_int * cap)()
+    kp = (C.c_int * cap)()
+    v = (C.c_double * cap)()
+    n = lib.pn_coupling_table(int(order), k, d, kp, v, cap)
+    if n < 0:
+        raise ValueError("bad order")
+    return [(k[i], d[i], kp[i], v[i]) for i in range(n)]

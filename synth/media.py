@@ -112,6 +112,11 @@ class Medium:
     q00: List[np.ndarray] = field(default_factory=list)   # one emission field per RHS
     bc: int = 0                                            # 0 vacuum, 1 periodic
 
+    def __post_init__(self):
+        # scalars are FP32 inputs like the fields
+        self.g = float(np.float32(self.g))
+        self.sigma_t_min = float(np.float32(self.sigma_t_min))
+
     @property
     def nrhs(self):
         return len(self.q00)

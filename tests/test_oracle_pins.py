@@ -170,7 +170,7 @@ def test_vectorised_assembly_and_matrix_free_match_row_loop(order, bc):
 
 
 def test_p1_single_cell_by_hand():
-    st, alb, g = 4.0, 0.75, 0.2
+    st, alb, g = 4.0, 0.75, float(np.float32(0.2))
     shp = (1, 1, 1)
     A, lay = assemble(1, (1, 1, 1), np.full(shp, st), np.full(shp, alb), g, 0.0)
     c = 1 / sqrt(3)
@@ -216,6 +216,7 @@ def test_uniform_periodic_anisotropic_source():
     m = config_uniform_periodic(n=3, order=order, sigma_t=5.0, albedo=0.8, g=g)
     A, lay = assemble(order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min, bc=1)
     st, ss = float(np.float32(5.0)), float(np.float32(5.0)) * float(np.float32(0.8))
+    g = float(np.float32(g))
     q = np.arange(1.0, lay.ncoeff + 1)
     b = np.zeros(lay.n)
     for k in range(lay.ncoeff):
@@ -231,7 +232,7 @@ def test_periodic_fourier_mode(order):
     dims = (8, 6, 4)
     h = 1.0 / dims[0]
     kappa = np.array([2 * pi * 1 / (dims[0] * h), 2 * pi * 2 / (dims[1] * h), 2 * pi * 1 / (dims[2] * h)])
-    st, alb, g = 3.0, 0.6, 0.35
+    st, alb, g = 3.0, 0.6, float(np.float32(0.35))
     shp = (dims[2], dims[1], dims[0])
     st32, alb32 = np.float32(st), np.float32(alb)
     A, lay = assemble(order, dims, np.full(shp, st32), np.full(shp, alb32), g, 0.0, bc=1)
@@ -307,7 +308,7 @@ def test_p1_schur_complement_is_diffusion():
     h = 1.0 / 3
     st = np.maximum(m.sigma_t.astype(np.float64), m.sigma_t_min)
     ss = m.albedo.astype(np.float64) * st
-    sp_ = st - m.g * ss
+    sp_ = st - float(np.float32(m.g)) * ss
     n = 3
     W = np.zeros((nc, nc))
     idx = lambda x, y, z: (z * n + y) * n + x
