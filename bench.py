@@ -1,0 +1,192 @@
+"""Benchmark: time to an FP64-equivalent relative residual of 1e-8 for P5 on a
+128^3 heterogeneous (nebula-like) medium, on one MI355X.
+
+One step = one complete solve A u = Q from u = 0 to ||Q - A u|| <= 1e-8 ||Q||
+(FP32 stencil + Krylov vectors, FP64 dot products, scalars and refinement
+residual), inputs resident in HBM.  Prints one JSON line.
+
+Also reported (JSON keys):
+  roofline      the stencil apply (the dominant kernel of the Krylov loop),
+                timed with HIP events on the solver stream: algorithmic bytes
+                per apply (8 B per unknown: read x, write y; plus 8 B per
+                cell of medium) / mean apply time, against the 8 TB/s HBM peak.
+  cpu_baseline  the FP64 oracle (NumPy, one thread) timed for one CGLS
+                iteration at the full size, scaled by the GPU solve's
+                iteration count.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "P5 128^3 time-to-1e-8 residual (plain vs learned+mixed); stencil HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("pn_kernels.h", "pn_tables.h", "pn_api.hip"):
+        with open(os.path.join(ROOT, "paper_1807_00410_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_hash, ms_per_apply):
+    """HBM bytes per apply from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "stencil_p5_128_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_apply")
+
+
+def cpu_baseline(medium, gpu_iters):
+    """One FP64 CGLS iteration of the oracle at the full size (A p, A^T r and
+    the vector updates), scaled by the number of iterations the GPU solve
+    took.  NumPy element-wise work runs on one thread."""
+    import numpy as np
+    from oracle.apply import Operator
+    op = Operator(medium.order, medium.dims, medium.sigma_t, medium.albedo, medium.g, medium.sigma_t_min)
+    rng = np.random.default_rng(0)
+    p = rng.normal(size=op.n)
+    r = rng.normal(size=op.n)
+    x = np.zeros(op.n)
+    t0 = time.perf_counter()
+    q = op.matvec(p)
+    alpha = float(r @ r) / float(q @ q)
+    x += alpha * p
+    r -= alpha * q
+    s = op.rmatvec(r)
+    gamma = float(s @ s)
+    p = s + (gamma / (gamma + 1.0)) * p
+    t_iter = time.perf_counter() - t0
+    return {"value": t_iter * gpu_iters, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": "one FP64 CGLS iteration (A p, A^T r, vector updates) of the NumPy oracle on the full "
+                      "P5 128^3 system (%.1f s), scaled by the %d iterations of the GPU solve" % (t_iter, gpu_iters),
+            "seconds_per_iteration": t_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--order", type=int, default=5)
+    ap.add_argument("--g", type=float, default=0.0)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--inner-tol", type=float, default=1e-3)
+    ap.add_argument("--apply-iters", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the pure FP64 Krylov comparison solve")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from synth import config_p5_nebula
+    from paper_1807_00410_amd.solver import Solver
+
+    t0 = time.perf_counter()
+    m = config_p5_nebula(n=args.n, seed=3, g=args.g, order=args.order)
+    print("[bench] medium %s generated in %.1fs" % (m.name, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    st = torch.as_tensor(m.sigma_t).to(dev)
+    al = torch.as_tensor(m.albedo).to(dev)
+    q00 = torch.as_tensor(m.q00[0]).to(dev)
+    s = Solver(m.order, m.dims, st, al, g=m.g, sigma_t_min=m.sigma_t_min)
+    rhs = s.rhs_from_q00(q00)
+    x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def one_solve():
+        return s.solve(rhs, x=x, tol=args.tol, inner_tol=args.inner_tol, raise_on_fail=True)
+
+    for i in range(args.warmup):
+        _, info = one_solve()
+        print("[bench] warmup %d: %.3fs iters %d rel %.3g" % (i, info["seconds"], info["inner_iters"],
+                                                              info["rel_residual"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    times, infos = [], []
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = one_solve()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        infos.append(info)
+        print("[bench] step %d: %.3fs iters %d outer %d rel %.3g" % (i, times[-1], info["inner_iters"],
+                                                                     info["outer_iters"], info["rel_residual"]),
+              file=sys.stderr, flush=True)
+    total = time.perf_counter() - t_all
+    sec = sum(times) / len(times)
+
+    # stencil roofline (HIP events on the solver stream)
+    ms_apply = s.bench_apply(args.apply_iters, transpose=False)
+    ms_apply_t = s.bench_apply(args.apply_iters, transpose=True)
+    cells = m.dims[0] * m.dims[1] * m.dims[2]
+    alg_bytes = 8 * s.n + 8 * cells
+    achieved = alg_bytes / (ms_apply * 1e-3) / 1e9
+    khash = source_hash()
+    traffic = load_traffic(khash, ms_apply)
+
+    fp64 = None
+    if not args.no_fp64:
+        xx = torch.zeros_like(x)
+        _, i64 = s.solve(rhs, x=xx, tol=args.tol, precision="fp64", raise_on_fail=False)
+        fp64 = {"seconds": i64["seconds"], "iters": i64["inner_iters"], "rel_residual": i64["rel_residual"],
+                "status": i64["status"]}
+        print("[bench] fp64 CGLS: %.3fs iters %d" % (i64["seconds"], i64["inner_iters"]), file=sys.stderr,
+              flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "P%d nebula %d^3 (32 Gaussian blobs x fBm, sigma_t in [0,200], albedo 0.95, "
+                               "g=%g, 2 point sources), vacuum boundary, tol %g"
+                               % (m.order, args.n, m.g, args.tol),
+                   "unknowns": s.n, "solver": "FP32 CGLS + FP64 dots/refinement (plain)"},
+        "iters": infos[-1]["inner_iters"],
+        "outer_iters": infos[-1]["outer_iters"],
+        "rel_residual": infos[-1]["rel_residual"],
+        "wall_s_timed_region": total,
+        "apply_ms": ms_apply,
+        "apply_t_ms": ms_apply_t,
+        "fp64_krylov": fp64,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_apply": alg_bytes,
+                     "kernel": "k_stencil<5,float,APPLY> (padded lattice)", "source_hash": khash},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, ~20-30 s)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(m, infos[-1]["inner_iters"])
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -163,6 +163,22 @@ pn_status pn_residual64(pn_ctx* ctx, const float* rhs, const double* x,
 pn_status pn_solve(pn_ctx* ctx, const float* rhs, double* x, double tol,
                    const pn_solve_opts* opts, pn_solve_info* info);
 
+/* Times `iters` back-to-back FP32 applies (transpose selects A^T) on the
+ * library's internal padded workspace -- the apply of the Krylov loop --
+ * with HIP events on the context stream; writes the mean milliseconds per
+ * apply to *ms_per_apply (host).  Synchronous.  For benchmarking. */
+pn_status pn_bench_apply(pn_ctx* ctx, int iters, int transpose, double* ms_per_apply);
+
+/* Launch tuning: planes of z handled per thread block in the stencil apply
+ * (0 = automatic).  Results do not depend on it (bitwise). */
+pn_status pn_set_zchunk(pn_ctx* ctx, int zchunk);
+int pn_get_zchunk(const pn_ctx* ctx);
+
+/* Coupling table compiled into the library for `order`: writes up to `cap`
+ * entries (row k, axis d, column k', value int omega_d Y^k Y^k') into the
+ * host arrays and returns the total count (-1 on bad arguments). */
+int pn_coupling_table(int order, int* k, int* d, int* kp, double* v, int cap);
+
 /* Frees the context and its workspace.  NULL is ignored. */
 void pn_destroy(pn_ctx* ctx);
 

@@ -62,6 +62,7 @@ SIGNATURES = [
                            C.POINTER(PnSolveInfo)]),
     ("pn_destroy", None, [C.c_void_p]),
     ("pn_last_error", C.c_char_p, [C.c_void_p]),
+    ("pn_bench_apply", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     ("pn_set_zchunk", C.c_int, [C.c_void_p, C.c_int]),
     ("pn_get_zchunk", C.c_int, [C.c_void_p]),
     ("pn_coupling_table", C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),

@@ -11,7 +11,17 @@
 #include <string>
 
 #include "../../include/pn.h"
-#include "pn_kernels.h"
+#include "pn_launch.h"
+
+namespace pn {  // instantiated in pn_order_N.hip
+extern template hipError_t launch_order<1>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<2>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<3>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<4>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<5>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<6>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<7>(int, bool, bool, const StencilArgs&, hipStream_t);
+}  // namespace pn
 
 using namespace pn;
 
@@ -31,11 +41,16 @@ struct pn_ctx {
   int off[kMaxCoeff] = {};
   int ext[kMaxCoeff][3] = {};
   int cls[kMaxCoeff][3] = {};
-  float2* med = nullptr;
-  // FP32 Krylov workspace (r ping-pong, s, p, q, d)
+  float2* med = nullptr;    // padded cells (sigma_t thresholded, albedo)
+  float2* med32 = nullptr;  // padded cells (sigma_a, sigma_s) FP32
+  // padded lattice geometry (see StencilArgs)
+  int PX = 0, PY = 0, plane = 0, CX = 0, cplane = 0;
+  long long cs = 0, nv = 0;  // coefficient stride, padded vector length
+  // FP32 Krylov workspace on the padded lattice (r ping-pong, s, p, q, d, rhs)
   float* r32[2] = {nullptr, nullptr};
-  float *s32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
-  // FP64 workspace, allocated on first use
+  float *s32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr, *b32 = nullptr;
+  double* x64 = nullptr;    // FP64 iterate (padded)
+  // FP64 Krylov workspace, allocated on first use
   double* r64[2] = {nullptr, nullptr};
   double *s64 = nullptr, *p64 = nullptr, *q64 = nullptr, *d64 = nullptr;
   DevState* st = nullptr;
@@ -78,6 +93,13 @@ static void set_geometry(pn_ctx* c, int zchunk) {
   c->Ex = c->nx + (per ? 0 : 1);
   c->Ey = c->ny + (per ? 0 : 1);
   c->Ez = c->nz + (per ? 0 : 1);
+  c->PX = c->Ex + 2;
+  c->PY = c->Ey + 2;
+  c->plane = c->PX * c->PY;
+  c->CX = c->nx + 2;
+  c->cplane = c->CX * (c->ny + 2);
+  c->cs = (((long long)c->plane * (c->Ez + 2)) + 63) / 64 * 64;
+  c->nv = c->cs * c->nc;
   c->ncb = (c->Ex * c->Ey + kBlock - 1) / kBlock;
   if (zchunk <= 0) {
     // aim at ~2048 blocks (8 per CU), at least 4 planes per chunk
@@ -96,40 +118,75 @@ static StencilArgs base_args(const pn_ctx* c) {
   std::memset(&a, 0, sizeof(a));
   a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
   a.Ex = c->Ex; a.Ey = c->Ey; a.Ez = c->Ez;
-  a.periodic = c->bc == PN_BC_PERIODIC;
+  a.PX = c->PX; a.PY = c->PY; a.plane = c->plane;
+  a.CX = c->CX; a.cplane = c->cplane;
+  a.cs = c->cs;
   a.zchunk = c->zchunk; a.nzc = c->nzc; a.ncb = c->ncb; a.nblocks = c->nblocks;
   a.invh = 1.0 / c->h;
   a.tsign = 1.0;
   double gp = 1.0;
   for (int l = 0; l < 8; ++l) { a.omg[l] = 1.0 - gp; gp *= (double)c->g; }
-  for (int k = 0; k < c->nc; ++k) a.off[k] = c->off[k];
   a.med = c->med;
+  a.med32 = c->med32;
   return a;
 }
 
+static PackArgs pack_args(const pn_ctx* c) {
+  PackArgs p;
+  std::memset(&p, 0, sizeof(p));
+  p.nc = c->nc; p.PX = c->PX; p.PY = c->PY; p.plane = c->plane; p.cs = c->cs;
+  for (int k = 0; k < c->nc; ++k) {
+    p.off[k] = c->off[k];
+    p.ex[k] = c->ext[k][0]; p.ey[k] = c->ext[k][1]; p.ez[k] = c->ext[k][2];
+  }
+  return p;
+}
+
+// DIR 0: padded <- packed; 1: packed <- padded; 2: packed += padded
+template <typename TS, typename TD, int DIR>
+static hipError_t launch_pack(const pn_ctx* c, const TS* src, TD* dst, hipStream_t s) {
+  long long maxsz = 0;
+  for (int k = 0; k < c->nc; ++k) {
+    long long sz = (long long)c->ext[k][0] * c->ext[k][1] * c->ext[k][2];
+    if (sz > maxsz) maxsz = sz;
+  }
+  long long bx = (maxsz + kBlock - 1) / kBlock;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL((k_pack<TS, TD, DIR>), dim3((unsigned)bx, c->nc), dim3(kBlock), 0, s, src, dst, pack_args(c));
+  return hipGetLastError();
+}
+
+// Dispatch on order (one translation unit per order) and boundary type; APPLY
+// launches reduce ||y||^2 only when a.partials is set (the Krylov loop), the
+// other modes always do.
 template <typename T, int MODE, typename TO>
-static hipError_t launch_stencil(int order, const StencilArgs& a, hipStream_t s) {
-  dim3 grid(a.nblocks), block(kBlock);
-  switch (order) {
-    case 1: hipLaunchKernelGGL((k_stencil<1, T, MODE, TO>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_stencil<2, T, MODE, TO>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_stencil<3, T, MODE, TO>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_stencil<4, T, MODE, TO>), grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_stencil<5, T, MODE, TO>), grid, block, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_stencil<6, T, MODE, TO>), grid, block, 0, s, a); break;
-    case 7: hipLaunchKernelGGL((k_stencil<7, T, MODE, TO>), grid, block, 0, s, a); break;
+static hipError_t launch_stencil(const pn_ctx* c, const StencilArgs& a, hipStream_t s) {
+  const bool per = c->bc == PN_BC_PERIODIC;
+  const bool norm = !(MODE == M_APPLY && a.partials == nullptr);
+  int kind;
+  if constexpr (sizeof(T) == 4) kind = (MODE == M_APPLY) ? K_F32_APPLY : K_F32_TRANSR;
+  else if constexpr (MODE == M_APPLY) kind = K_F64_APPLY;
+  else if constexpr (MODE == M_TRANSR) kind = K_F64_TRANSR;
+  else kind = (sizeof(TO) == 4) ? K_F64_RESID32 : K_F64_RESID64;
+  switch (c->order) {
+    case 1: return launch_order<1>(kind, per, norm, a, s);
+    case 2: return launch_order<2>(kind, per, norm, a, s);
+    case 3: return launch_order<3>(kind, per, norm, a, s);
+    case 4: return launch_order<4>(kind, per, norm, a, s);
+    case 5: return launch_order<5>(kind, per, norm, a, s);
+    case 6: return launch_order<6>(kind, per, norm, a, s);
+    case 7: return launch_order<7>(kind, per, norm, a, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 static void free_all(pn_ctx* c) {
   if (!c) return;
   if (c->gexec32) hipGraphExecDestroy(c->gexec32);
   if (c->gexec64) hipGraphExecDestroy(c->gexec64);
-  hipFree(c->med);
+  hipFree(c->med); hipFree(c->med32);
   for (int i = 0; i < 2; ++i) { hipFree(c->r32[i]); hipFree(c->r64[i]); }
-  hipFree(c->s32); hipFree(c->p32); hipFree(c->q32); hipFree(c->d32);
+  hipFree(c->s32); hipFree(c->p32); hipFree(c->q32); hipFree(c->d32); hipFree(c->b32); hipFree(c->x64);
   hipFree(c->s64); hipFree(c->p64); hipFree(c->q64); hipFree(c->d64);
   hipFree(c->st); hipFree(c->partials); hipFree(c->flag);
   if (c->st_host) hipHostFree(c->st_host);
@@ -233,12 +290,16 @@ extern "C" pn_status pn_setup(int order, const pn_grid* grid, const pn_medium* m
   SETUP_HIP(hipStreamCreateWithFlags(&c->sstream, hipStreamNonBlocking));
   SETUP_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   SETUP_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
-  SETUP_HIP(hipMalloc(&c->med, sizeof(float2) * cells));
-  for (int i = 0; i < 2; ++i) SETUP_HIP(hipMalloc(&c->r32[i], sizeof(float) * n));
-  SETUP_HIP(hipMalloc(&c->s32, sizeof(float) * n));
-  SETUP_HIP(hipMalloc(&c->p32, sizeof(float) * n));
-  SETUP_HIP(hipMalloc(&c->q32, sizeof(float) * n));
-  SETUP_HIP(hipMalloc(&c->d32, sizeof(float) * n));
+  const long long pcells = (long long)(c->nx + 2) * (c->ny + 2) * (c->nz + 2);
+  SETUP_HIP(hipMalloc(&c->med, sizeof(float2) * pcells));
+  SETUP_HIP(hipMalloc(&c->med32, sizeof(float2) * pcells));
+  float** v32[] = {&c->r32[0], &c->r32[1], &c->s32, &c->p32, &c->q32, &c->d32, &c->b32};
+  for (float** v : v32) {
+    SETUP_HIP(hipMalloc(v, sizeof(float) * c->nv));
+    SETUP_HIP(hipMemsetAsync(*v, 0, sizeof(float) * c->nv, c->stream));  // zero halo invariant
+  }
+  SETUP_HIP(hipMalloc(&c->x64, sizeof(double) * c->nv));
+  SETUP_HIP(hipMemsetAsync(c->x64, 0, sizeof(double) * c->nv, c->stream));
   SETUP_HIP(hipMalloc(&c->st, sizeof(DevState)));
   SETUP_HIP(hipHostMalloc(&c->st_host, sizeof(DevState), hipHostMallocDefault));
   SETUP_HIP(hipMalloc(&c->partials, sizeof(double) * 2 * c->max_blocks));
@@ -246,8 +307,8 @@ extern "C" pn_status pn_setup(int order, const pn_grid* grid, const pn_medium* m
   SETUP_HIP(hipHostMalloc(&c->flag_host, sizeof(int), hipHostMallocDefault));
 
   SETUP_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
-  hipLaunchKernelGGL(k_medium_prep, dim3(grid_for(cells)), dim3(kBlock), 0, c->stream, med->sigma_t,
-                     med->albedo, c->thr, c->med, cells, c->flag);
+  hipLaunchKernelGGL(k_medium_prep, dim3(grid_for(pcells)), dim3(kBlock), 0, c->stream, med->sigma_t,
+                     med->albedo, c->thr, c->nx, c->ny, c->nz, per, c->med32, c->med, c->flag);
   SETUP_HIP(hipGetLastError());
   SETUP_HIP(hipMemcpyAsync(c->flag_host, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   SETUP_HIP(hipStreamSynchronize(c->stream));
@@ -283,14 +344,27 @@ extern "C" pn_status pn_layout_query(const pn_ctx* c, pn_layout* L) {
   return PN_OK;
 }
 
+static pn_status ensure64(pn_ctx* c) {
+  if (c->s64) return PN_OK;
+  double** v[] = {&c->r64[0], &c->r64[1], &c->s64, &c->p64, &c->q64, &c->d64};
+  for (double** p : v) {
+    PN_HIP(hipMalloc(p, sizeof(double) * c->nv));
+    PN_HIP(hipMemsetAsync(*p, 0, sizeof(double) * c->nv, c->stream));
+  }
+  return PN_OK;
+}
+
 extern "C" pn_status pn_apply(pn_ctx* c, const float* x, float* y, int transpose) {
   if (!c) return PN_ERR_ARG;
   if (!x || !y) return fail(c, PN_ERR_ARG, "x or y is NULL");
   if ((const void*)x == (const void*)y) return fail(c, PN_ERR_ARG, "x and y must not alias");
+  // packed -> padded (p32), apply into q32, padded -> packed
+  PN_HIP((launch_pack<float, float, 0>(c, x, c->p32, c->stream)));
   StencilArgs a = base_args(c);
   a.tsign = transpose ? -1.0 : 1.0;
-  a.x = x; a.y = y;
-  PN_HIP((launch_stencil<float, M_APPLY, float>(c->order, a, c->stream)));
+  a.x = c->p32; a.y = c->q32;
+  PN_HIP((launch_stencil<float, M_APPLY, float>(c, a, c->stream)));
+  PN_HIP((launch_pack<float, float, 1>(c, c->q32, y, c->stream)));
   return PN_OK;
 }
 
@@ -298,31 +372,47 @@ extern "C" pn_status pn_apply64(pn_ctx* c, const double* x, double* y, int trans
   if (!c) return PN_ERR_ARG;
   if (!x || !y) return fail(c, PN_ERR_ARG, "x or y is NULL");
   if ((const void*)x == (const void*)y) return fail(c, PN_ERR_ARG, "x and y must not alias");
+  pn_status e = ensure64(c);
+  if (e != PN_OK) return e;
+  PN_HIP((launch_pack<double, double, 0>(c, x, c->p64, c->stream)));
   StencilArgs a = base_args(c);
   a.tsign = transpose ? -1.0 : 1.0;
-  a.x = x; a.y = y;
-  PN_HIP((launch_stencil<double, M_APPLY, double>(c->order, a, c->stream)));
+  a.x = c->p64; a.y = c->q64;
+  PN_HIP((launch_stencil<double, M_APPLY, double>(c, a, c->stream)));
+  PN_HIP((launch_pack<double, double, 1>(c, c->q64, y, c->stream)));
   return PN_OK;
 }
 
-static pn_status ensure64(pn_ctx* c) {
-  if (c->s64) return PN_OK;
-  const size_t b = sizeof(double) * c->n;
-  for (int i = 0; i < 2; ++i) PN_HIP(hipMalloc(&c->r64[i], b));
-  PN_HIP(hipMalloc(&c->s64, b));
-  PN_HIP(hipMalloc(&c->p64, b));
-  PN_HIP(hipMalloc(&c->q64, b));
-  PN_HIP(hipMalloc(&c->d64, b));
-  return PN_OK;
-}
-
-// r = Q - A x in FP64 arithmetic; r stored as TO; partials -> st->rtrue2, st->bb2.
-template <typename TO>
-static pn_status residual(pn_ctx* c, const float* rhs, const double* x, TO* r, hipStream_t s) {
+// Times `iters` back-to-back FP32 applies on the padded workspace (the apply
+// of the Krylov loop) with HIP events on the context stream.
+extern "C" pn_status pn_bench_apply(pn_ctx* c, int iters, int transpose, double* ms_per_apply) {
+  if (!c || iters < 1 || !ms_per_apply) return c ? fail(c, PN_ERR_ARG, "bad arguments") : PN_ERR_ARG;
+  hipEvent_t e0, e1;
+  PN_HIP(hipEventCreate(&e0));
+  PN_HIP(hipEventCreate(&e1));
   StencilArgs a = base_args(c);
-  a.x = x; a.x2 = rhs; a.y = r;
+  a.tsign = transpose ? -1.0 : 1.0;
+  a.x = c->p32; a.y = c->q32;
+  PN_HIP((launch_stencil<float, M_APPLY, float>(c, a, c->stream)));  // warm-up
+  PN_HIP(hipEventRecord(e0, c->stream));
+  for (int i = 0; i < iters; ++i) PN_HIP((launch_stencil<float, M_APPLY, float>(c, a, c->stream)));
+  PN_HIP(hipEventRecord(e1, c->stream));
+  PN_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  PN_HIP(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms_per_apply = ms / iters;
+  return PN_OK;
+}
+
+// r = Q - A x in FP64 arithmetic on padded vectors; partials -> st->rtrue2, st->bb2.
+template <typename TO>
+static pn_status residual(pn_ctx* c, const float* rhs_pad, const double* x_pad, TO* r_pad, hipStream_t s) {
+  StencilArgs a = base_args(c);
+  a.x = x_pad; a.x2 = rhs_pad; a.y = r_pad;
   a.partials = c->partials;
-  PN_HIP((launch_stencil<double, M_RESID, TO>(c->order, a, s)));
+  PN_HIP((launch_stencil<double, M_RESID, TO>(c, a, s)));
   hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kBlock), 0, s, c->st, c->partials, c->nblocks);
   PN_HIP(hipGetLastError());
   return PN_OK;
@@ -331,36 +421,35 @@ static pn_status residual(pn_ctx* c, const float* rhs, const double* x, TO* r, h
 extern "C" pn_status pn_residual64(pn_ctx* c, const float* rhs, const double* x, double* r, double* rel) {
   if (!c) return PN_ERR_ARG;
   if (!rhs || !x) return fail(c, PN_ERR_ARG, "rhs or x is NULL");
-  pn_status s = PN_OK;
-  if (!r) {
-    s = ensure64(c);
-    if (s != PN_OK) return s;
-    r = c->r64[0];
-  }
-  s = residual<double>(c, rhs, x, r, c->stream);
+  pn_status s = ensure64(c);
   if (s != PN_OK) return s;
+  PN_HIP((launch_pack<float, float, 0>(c, rhs, c->b32, c->stream)));
+  PN_HIP((launch_pack<double, double, 0>(c, x, c->x64, c->stream)));
+  s = residual<double>(c, c->b32, c->x64, c->r64[0], c->stream);
+  if (s != PN_OK) return s;
+  if (r) PN_HIP((launch_pack<double, double, 1>(c, c->r64[0], r, c->stream)));
   PN_HIP(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
   PN_HIP(hipStreamSynchronize(c->stream));
   if (rel) *rel = c->st_host->bb2 > 0.0 ? std::sqrt(c->st_host->rtrue2 / c->st_host->bb2) : 0.0;
   return PN_OK;
 }
 
-// One CGLS iteration on vectors of type T (r ping-pong rin -> rout).
+// One CGLS iteration on padded vectors of type T (r ping-pong rin -> rout).
 template <typename T>
 static hipError_t enqueue_iteration(pn_ctx* c, T* d, T* p, T* q, T* s, const T* rin, T* rout, hipStream_t st) {
   StencilArgs a = base_args(c);
   a.st = c->st;
   a.partials = c->partials;
   a.x = p; a.y = q; a.tsign = 1.0;
-  hipError_t e = launch_stencil<T, M_APPLY, T>(c->order, a, st);
+  hipError_t e = launch_stencil<T, M_APPLY, T>(c, a, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->nblocks);
   a.x = rin; a.x2 = q; a.y = s; a.y2 = rout; a.tsign = -1.0;
-  e = launch_stencil<T, M_TRANSR, T>(c->order, a, st);
+  e = launch_stencil<T, M_TRANSR, T>(c, a, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->nblocks);
-  hipLaunchKernelGGL((k_update_xp<T>), dim3(grid_for(c->n / (sizeof(T) == 4 ? 4 : 1) + 1)), dim3(kBlock), 0, st,
-                     d, p, (const T*)s, c->n, (const DevState*)c->st);
+  hipLaunchKernelGGL((k_update_xp<T>), dim3(grid_for(c->nv / (sizeof(T) == 4 ? 4 : 1) + 1)), dim3(kBlock), 0, st,
+                     d, p, (const T*)s, (long)c->nv, (const DevState*)c->st);
   return hipGetLastError();
 }
 
@@ -382,9 +471,10 @@ static pn_status build_graph(pn_ctx* c, int iters, T* d, T* p, T* q, T* s, T* r0
   return PN_OK;
 }
 
+// Iterative refinement around CGLS on the padded lattice.  b32 holds Q and
+// x64 the FP64 iterate on entry; x64 holds the result on exit.
 template <typename T>
-static pn_status solve_impl(pn_ctx* c, const float* rhs, double* x, double tol, const pn_solve_opts& o,
-                            pn_solve_info* info) {
+static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_solve_info* info) {
   T *r0, *r1, *s, *p, *q, *d;
   hipGraphExec_t* gexec;
   int* giters;
@@ -410,16 +500,12 @@ static pn_status solve_impl(pn_ctx* c, const float* rhs, double* x, double tol, 
   init.max_iters = o.max_iter;
   PN_HIP(hipMemcpyAsync(c->st, &init, sizeof(DevState), hipMemcpyHostToDevice, ss));
   PN_HIP(hipStreamSynchronize(ss));
-  if (!o.use_guess) {
-    hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(c->n)), dim3(kBlock), 0, ss, x, c->n, 0.0);
-    PN_HIP(hipGetLastError());
-  }
   pn_status result = PN_ERR_NOT_CONVERGED;
   int outer = 0;
   double rel = 0.0, bnorm = 0.0;
   if (info) info->nhistory = 0;
   for (;;) {
-    pn_status e = residual<T>(c, rhs, x, r0, ss);
+    pn_status e = residual<T>(c, c->b32, c->x64, r0, ss);
     if (e != PN_OK) return e;
     PN_HIP(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, ss));
     PN_HIP(hipStreamSynchronize(ss));
@@ -427,7 +513,7 @@ static pn_status solve_impl(pn_ctx* c, const float* rhs, double* x, double tol, 
     ++outer;
     bnorm = std::sqrt(h.bb2);
     if (h.bb2 == 0.0) {  // Q = 0: the solution is 0
-      hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(c->n)), dim3(kBlock), 0, ss, x, c->n, 0.0);
+      hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, c->x64, (long)c->nv, 0.0);
       PN_HIP(hipGetLastError());
       rel = 0.0;
       result = PN_OK;
@@ -443,20 +529,20 @@ static pn_status solve_impl(pn_ctx* c, const float* rhs, double* x, double tol, 
     double itol = o.inner_tol;
     if constexpr (sizeof(T) == 8) itol = 0.5 * tol / rel;  // FP64: go all the way
     if (itol >= 1.0) itol = 0.5;
-    hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(c->n)), dim3(kBlock), 0, ss, d, c->n, T(0));
+    hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, d, (long)c->nv, T(0));
     StencilArgs a = base_args(c);
-    a.x = r0; a.y = s; a.y2 = p; a.tsign = -1.0; a.partials = c->partials;
-    PN_HIP((launch_stencil<T, M_APPLY, T>(c->order, a, ss)));
+    a.x = r0; a.y = s; a.tsign = -1.0; a.partials = c->partials;
+    PN_HIP((launch_stencil<T, M_APPLY, T>(c, a, ss)));
     hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials, c->nblocks, itol * itol);
     PN_HIP(hipGetLastError());
+    PN_HIP(hipMemcpyAsync(p, s, sizeof(T) * c->nv, hipMemcpyDeviceToDevice, ss));  // p = s
     for (;;) {
       PN_HIP(hipGraphLaunch(*gexec, ss));
       PN_HIP(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, ss));
       PN_HIP(hipStreamSynchronize(ss));
       if (c->st_host->done || c->st_host->stop) break;
     }
-    // the last graph may have stopped with stop set but done unset: x update already applied
-    hipLaunchKernelGGL((k_add_to64<T>), dim3(grid_for(c->n)), dim3(kBlock), 0, ss, x, (const T*)d, c->n);
+    hipLaunchKernelGGL((k_axpy64<T>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, c->x64, (const T*)d, (long)c->nv);
     PN_HIP(hipGetLastError());
   }
   if (info) {
@@ -482,21 +568,31 @@ extern "C" pn_status pn_solve(pn_ctx* c, const float* rhs, double* x, double tol
   if (o.precision != PN_FP32_IR && o.precision != PN_FP64) return fail(c, PN_ERR_ARG, "unknown precision");
   if (info) std::memset(info, 0, sizeof(*info));
   const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t ss = c->sstream;
   // order the solve after the caller's pending work
   PN_HIP(hipEventRecord(c->ev_in, c->stream));
-  PN_HIP(hipStreamWaitEvent(c->sstream, c->ev_in, 0));
+  PN_HIP(hipStreamWaitEvent(ss, c->ev_in, 0));
   // non-finite right-hand side
-  PN_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), c->sstream));
-  hipLaunchKernelGGL(k_check_finite, dim3(grid_for(c->n)), dim3(kBlock), 0, c->sstream, rhs, c->n, c->flag);
+  PN_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), ss));
+  hipLaunchKernelGGL(k_check_finite, dim3(grid_for(c->n)), dim3(kBlock), 0, ss, rhs, c->n, c->flag);
   PN_HIP(hipGetLastError());
-  PN_HIP(hipMemcpyAsync(c->flag_host, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->sstream));
-  PN_HIP(hipStreamSynchronize(c->sstream));
+  PN_HIP(hipMemcpyAsync(c->flag_host, c->flag, sizeof(int), hipMemcpyDeviceToHost, ss));
+  PN_HIP(hipStreamSynchronize(ss));
   if (*c->flag_host) return fail(c, PN_ERR_NONFINITE, "right-hand side contains NaN or Inf");
-  pn_status s = (o.precision == PN_FP64) ? solve_impl<double>(c, rhs, x, tol, o, info)
-                                          : solve_impl<float>(c, rhs, x, tol, o, info);
-  PN_HIP(hipEventRecord(c->ev_out, c->sstream));
+  // packed -> padded: Q into b32, the initial iterate into x64
+  PN_HIP((launch_pack<float, float, 0>(c, rhs, c->b32, ss)));
+  if (o.use_guess) {
+    PN_HIP((launch_pack<double, double, 0>(c, x, c->x64, ss)));
+  } else {
+    hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, c->x64, (long)c->nv, 0.0);
+    PN_HIP(hipGetLastError());
+  }
+  pn_status s = (o.precision == PN_FP64) ? solve_impl<double>(c, tol, o, info) : solve_impl<float>(c, tol, o, info);
+  // padded -> packed result (also after a failed solve: x is the last iterate)
+  PN_HIP((launch_pack<double, double, 1>(c, c->x64, x, ss)));
+  PN_HIP(hipEventRecord(c->ev_out, ss));
   PN_HIP(hipStreamWaitEvent(c->stream, c->ev_out, 0));
-  PN_HIP(hipStreamSynchronize(c->sstream));
+  PN_HIP(hipStreamSynchronize(ss));
   if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (s == PN_ERR_NOT_CONVERGED) fail(c, s, "tolerance not reached within max_iter / max_refine");
   if (s == PN_ERR_BREAKDOWN) fail(c, s, "CGLS breakdown");

@@ -30,6 +30,11 @@ namespace pn {
 constexpr int kBlock = 256;
 constexpr int kMaxCoeff = 64;
 
+// Minimum waves per SIMD the stencil kernels are compiled for (caps VGPRs).
+#ifndef PN_STENCIL_WPE
+#define PN_STENCIL_WPE 1
+#endif
+
 // ------------------------------------------------------------------ state --
 struct DevState {
   double gamma;   // ||s||^2 of the current normal-equation residual s = A^T r
@@ -52,21 +57,33 @@ struct DevState {
 
 enum Mode { M_APPLY = 0, M_TRANSR = 1, M_RESID = 2 };
 
+// Internal vectors live on a padded lattice shared by every coefficient:
+// coefficient k occupies [k*cs, (k+1)*cs); lattice point (x, y, z) of any
+// class sits at ((z+1)*PY + (y+1))*PX + (x+1) with PX = Ex + 2, PY = Ey + 2,
+// where Ex = nx + 1 (vacuum) or nx (periodic).  Entries outside a
+// coefficient's class extent -- the one-point halo and, for a class centred
+// along d, the position x_d = n_d -- are zero and stay zero: kernels never
+// store there and every element-wise update maps 0 to 0.  That makes every
+// neighbour load unconditional (vacuum: an out-of-domain read hits a zero).
+// Cells are padded the same way, their halo holding clamped (vacuum) or
+// wrapped (periodic) copies, so the parameter reads need no clamping either.
 struct StencilArgs {
   int nx, ny, nz;
-  int Ex, Ey, Ez;      // thread lattice: n + 1 per axis (vacuum) or n (periodic)
-  int periodic;
+  int Ex, Ey, Ez;      // lattice points per axis
+  int PX, PY, plane;   // padded pitches of a coefficient array, plane = PX*PY
+  int CX, cplane;      // padded cell pitches: CX = nx + 2, cplane = CX*(ny + 2)
+  long long cs;        // coefficient stride (elements)
   int zchunk, nzc, ncb, nblocks;
   double invh;         // 1 / h
   double tsign;        // +1: A, -1: A^T
   double omg[8];       // 1 - g^l, l = 0..7
-  int off[kMaxCoeff];  // offset of coefficient k in the vector (elements)
-  const float2* med;   // per cell (thresholded sigma_t, albedo)
+  const float2* med32; // padded cells (sigma_a, sigma_s) in FP32
+  const float2* med;   // padded cells (sigma_t, albedo) as given (FP64 kernels)
   const void* x;       // input vector (T); M_TRANSR: r
   const void* x2;      // M_TRANSR: q;  M_RESID: right-hand side (float)
   void* y;             // output vector
-  void* y2;            // M_APPLY: optional second copy of y; M_TRANSR: updated r
-  DevState* st;        // device scalars (alpha for M_TRANSR, done flag), may be null
+  void* y2;            // M_TRANSR: updated r
+  DevState* st;        // device scalars (alpha for M_TRANSR, stop/done flags), may be null
   double* partials;    // [nblocks][2] FP64 partial sums, may be null
 };
 
@@ -88,6 +105,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Access at a uniform base pointer plus a 32-bit byte offset (lets the
+// compiler use the scalar-base + vector-offset addressing mode).
+template <typename U>
+__device__ __forceinline__ U ldb(const U* base, unsigned boff) {
+  return *reinterpret_cast<const U*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename U>
+__device__ __forceinline__ void stb(U* base, unsigned boff, U v) {
+  *reinterpret_cast<U*>(reinterpret_cast<char*>(base) + boff) = v;
+}
 
 template <typename T>
 __device__ __forceinline__ T fmadd(T a, T b, T c);
@@ -118,13 +146,15 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 }
 
 // --------------------------------------------------------------- stencil --
-// T: arithmetic / vector type of the input (float or double).
-// TO: output element type.  MODE: M_APPLY  y = op(x)            [+ ||y||^2]
-//                                 M_TRANSR r' = r - alpha q, y = A^T r'
-//                                          [writes r' to y2; ||y||^2, ||r'||^2]
-//                                 M_RESID  y = Q - A x        [||y||^2, ||Q||^2]
-template <int N, typename T, int MODE, typename TO>
-__global__ void __launch_bounds__(kBlock) k_stencil(const StencilArgs a) {
+// T: arithmetic / vector type of the input (float or double).  TO: output
+// element type.  PER: periodic boundary.  NORM: write the FP64 block partial
+// sums of the squares below to a.partials (per thread, squares are summed in
+// T over the rows of one class -- at most 10 terms -- then added in FP64).
+//   M_APPLY  y = op(x)                         [||y||^2]
+//   M_TRANSR r' = r - alpha q, y = A^T r'      [writes r' to y2; ||y||^2, ||r'||^2]
+//   M_RESID  y = Q - A x                       [||y||^2, ||Q||^2]
+template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
+__global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil(const StencilArgs a) {
   using TB = Table<N>;
   constexpr int NC = TB::NC;
   constexpr int NCPL = TB::NCPL;
@@ -139,7 +169,6 @@ __global__ void __launch_bounds__(kBlock) k_stencil(const StencilArgs a) {
   const int y = act ? col / a.Ex : 0;
   const int z0 = zc * a.zchunk;
   const int z1 = min(z0 + a.zchunk, a.Ez);
-  const int per = a.periodic;
 
   const T* __restrict__ X = static_cast<const T*>(a.x);
   const T* __restrict__ X2 = static_cast<const T*>(a.x2);
@@ -149,72 +178,93 @@ __global__ void __launch_bounds__(kBlock) k_stencil(const StencilArgs a) {
   T alpha = T(0);
   if constexpr (MODE == M_TRANSR) alpha = T(a.st->alpha);
   const T tinvh = T(a.tsign * a.invh);
+  const long long cs = a.cs;
+
+  // Lane offsets inside a padded plane (own point and the four in-plane
+  // neighbours), kept as 32-bit BYTE offsets: every access is then a uniform
+  // 64-bit base (coefficient, plane) in SGPRs plus one 32-bit VGPR offset.
+  unsigned o, oxp, oxm, oyp, oym;
+  {
+    const int oi = (y + 1) * a.PX + (x + 1);
+    int ixp, ixm, iyp, iym;
+    if constexpr (PER) {
+      ixp = (y + 1) * a.PX + (x + 1 == a.nx ? 0 : x + 1) + 1;
+      ixm = (y + 1) * a.PX + (x == 0 ? a.nx - 1 : x - 1) + 1;
+      iyp = ((y + 1 == a.ny ? 0 : y + 1) + 1) * a.PX + x + 1;
+      iym = ((y == 0 ? a.ny - 1 : y - 1) + 1) * a.PX + x + 1;
+    } else {
+      ixp = oi + 1; ixm = oi - 1; iyp = oi + a.PX; iym = oi - a.PX;
+    }
+    o = (unsigned)oi * (unsigned)sizeof(T);
+    oxp = (unsigned)ixp * (unsigned)sizeof(T);
+    oxm = (unsigned)ixm * (unsigned)sizeof(T);
+    oyp = (unsigned)iyp * (unsigned)sizeof(T);
+    oym = (unsigned)iym * (unsigned)sizeof(T);
+  }
+  const unsigned oo = o / (unsigned)sizeof(T) * (unsigned)sizeof(TO);  // own point, output type
+  const unsigned orhs = o / (unsigned)sizeof(T) * 4u;                 // own point, float rhs
+  // padded cell (x-1, y-1) of a cell plane, bytes
+  const unsigned mo = (unsigned)(y * a.CX + x) * (unsigned)sizeof(float2);
+  const unsigned mcx = (unsigned)a.CX * (unsigned)sizeof(float2);
+  const bool okx0 = PER || x < a.nx;  // store predicate of classes centred in x
+  const bool oky0 = PER || y < a.ny;
+
+  // padded plane offset (elements) of lattice plane z (periodic planes wrap)
+  // The offset goes through readfirstlane: it is uniform anyway, and the
+  // opaque value keeps loop strength reduction from turning every one of the
+  // ~100 address streams into its own 64-bit induction variable in VGPRs.
+  auto zoff = [&](int z) -> long long {
+    if constexpr (PER) z = wrapi(z, a.nz);
+    return (long long)__builtin_amdgcn_readfirstlane((z + 1) * a.plane);
+  };
+  auto load = [&](auto KPc, long long zo, unsigned lo) -> T {
+    constexpr int KP = decltype(KPc)::value;
+    const long long base = (long long)KP * cs + zo;
+    if constexpr (MODE == M_TRANSR) return fmadd<T>(-alpha, ldb(X2 + base, lo), ldb(X + base, lo));
+    else return ldb(X + base, lo);
+  };
+  const float2* __restrict__ MED = (sizeof(T) == 4) ? a.med32 : a.med;
+  auto cells = [&](int z, T* sa, T* ss) {  // 4 cells (x-1|x, y-1|y) of cell plane z
+    const float2* __restrict__ mp = MED + (long long)(z + 1) * a.cplane;
+    const float2 c[4] = {ldb(mp, mo), ldb(mp, mo + 8u), ldb(mp, mo + mcx), ldb(mp, mo + mcx + 8u)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if constexpr (sizeof(T) == 4) {
+        sa[q] = c[q].x; ss[q] = c[q].y;
+      } else {  // exact in FP64: sigma_t (1 - albedo), sigma_t albedo
+        sa[q] = T(c[q].x) * (T(1) - T(c[q].y));
+        ss[q] = T(c[q].x) * T(c[q].y);
+      }
+    }
+  };
 
   double nrm0 = 0.0, nrm1 = 0.0;
-
-  // Flat index of coefficient KP at lattice point (i, j, k); -1 if outside.
-  auto index_of = [&](auto KPc, int i, int j, int k) -> int {
-    constexpr int KP = decltype(KPc)::value;
-    const int ex = a.nx + (per ? 0 : cls_x(KP));
-    const int ey = a.ny + (per ? 0 : cls_y(KP));
-    const int ez = a.nz + (per ? 0 : cls_z(KP));
-    if (per) {
-      i = wrapi(i, ex); j = wrapi(j, ey); k = wrapi(k, ez);
-    } else if ((unsigned)i >= (unsigned)ex || (unsigned)j >= (unsigned)ey || (unsigned)k >= (unsigned)ez) {
-      return -1;
-    }
-    return a.off[KP] + (k * ey + j) * ex + i;
-  };
-  auto val = [&](auto KPc, int i, int j, int k) -> T {
-    const int idx = index_of(KPc, i, j, k);
-    if (idx < 0) return T(0);
-    if constexpr (MODE == M_TRANSR) return fmadd<T>(-alpha, X2[idx], X[idx]);
-    else return X[idx];
-  };
-  auto cell = [&](int i, int j, int k) -> float2 {
-    if (per) {
-      i = wrapi(i, a.nx); j = wrapi(j, a.ny); k = wrapi(k, a.nz);
-    } else {
-      i = min(max(i, 0), a.nx - 1); j = min(max(j, 0), a.ny - 1); k = min(max(k, 0), a.nz - 1);
-    }
-    return a.med[(k * a.ny + j) * a.nx + i];
-  };
-
-  if (act) {
+  {  // lanes past the last column recompute column 0 and store nothing
     T cur[NC], nb[NC];
-    sfor<NC>([&](auto KPc) {
-      constexpr int KP = decltype(KPc)::value;
-      if constexpr (cls_z(KP) == 1) nb[KP] = val(KPc, x, y, z0);
-      else cur[KP] = val(KPc, x, y, z0 - 1);
-    });
-    // cells (x-1|x, y-1|y) of the plane below, index q = 2*dy + dx
-    float2 mprev[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) mprev[q] = cell(x - 1 + (q & 1), y - 1 + (q >> 1), z0 - 1);
-
-    for (int z = z0; z < z1; ++z) {
+    {
+      const long long zo0 = zoff(z0), zom = zoff(z0 - 1);
       sfor<NC>([&](auto KPc) {
         constexpr int KP = decltype(KPc)::value;
-        if constexpr (cls_z(KP) == 1) { cur[KP] = nb[KP]; nb[KP] = val(KPc, x, y, z + 1); }
-        else { nb[KP] = cur[KP]; cur[KP] = val(KPc, x, y, z); }
+        if constexpr (cls_z(KP) == 1) nb[KP] = load(KPc, zo0, o);
+        else cur[KP] = load(KPc, zom, o);
       });
-      float2 mcur[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) mcur[q] = cell(x - 1 + (q & 1), y - 1 + (q >> 1), z);
-      // Per-cell sigma_a = sigma_t (1 - albedo) and sigma_s = sigma_t albedo,
-      // index c = 4*dz + 2*dy + dx (0 = lower neighbour).  The row diagonal
-      // sigma_t - g^l sigma_s is formed as mean(sigma_a) + (1 - g^l) mean(sigma_s):
-      // the same number, without the cancellation of sigma_t - sigma_s when the
-      // albedo is close to 1.
-      T sa[8], ss[8];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        sa[q] = T(mprev[q].x) * (T(1) - T(mprev[q].y));
-        ss[q] = T(mprev[q].x) * T(mprev[q].y);
-        sa[4 + q] = T(mcur[q].x) * (T(1) - T(mcur[q].y));
-        ss[4 + q] = T(mcur[q].x) * T(mcur[q].y);
-      }
-      // class means (cells visited z-major, lower neighbour first)
+    }
+    T msa[8], mss[8];  // cells of the plane below (0..3) and of this plane (4..7)
+    cells(PER ? wrapi(z0 - 1, a.nz) : z0 - 1, msa, mss);
+
+#pragma clang loop unroll(disable)
+    for (int z = z0; z < z1; ++z) {
+      const long long zo = zoff(z), zon = zoff(z + 1);
+      sfor<NC>([&](auto KPc) {
+        constexpr int KP = decltype(KPc)::value;
+        if constexpr (cls_z(KP) == 1) { cur[KP] = nb[KP]; nb[KP] = load(KPc, zon, o); }
+        else { nb[KP] = cur[KP]; cur[KP] = load(KPc, zo, o); }
+      });
+      cells(z, msa + 4, mss + 4);
+      // Class means of sigma_a and sigma_s (cells visited z-major, lower
+      // neighbour first).  The row diagonal sigma_t - g^l sigma_s is formed as
+      // mean(sigma_a) + (1 - g^l) mean(sigma_s): the same number without the
+      // cancellation of sigma_t - sigma_s at albedo close to 1.
       T csa[8], css[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
@@ -227,8 +277,8 @@ __global__ void __launch_bounds__(kBlock) k_stencil(const StencilArgs a) {
           for (int dy = 1 - py; dy < 2; ++dy)
 #pragma unroll
             for (int dx = 1 - px; dx < 2; ++dx) {
-              s0 += sa[4 * dz + 2 * dy + dx];
-              s1 += ss[4 * dz + 2 * dy + dx];
+              s0 += msa[4 * dz + 2 * dy + dx];
+              s1 += mss[4 * dz + 2 * dy + dx];
               ++cnt;
             }
         const T inv = T(1) / T(cnt);
@@ -236,57 +286,76 @@ __global__ void __launch_bounds__(kBlock) k_stencil(const StencilArgs a) {
         css[c] = s1 * inv;
       }
 
-      // transport: differences formed once per (input, axis), fanned out to rows
-      T acc[NC];
-      sfor<NC>([&](auto K) { acc[decltype(K)::value] = T(0); });
-      T dcur = T(0);
-      sfor<NCPL>([&](auto Ic) {
-        constexpr int I = decltype(Ic)::value;
-        constexpr Coupling cp = TB::cpl.v[I];
-        constexpr bool first = (I == 0) || TB::cpl.v[I - 1].kp != cp.kp || TB::cpl.v[I - 1].d != cp.d;
-        if constexpr (first) {
-          constexpr int p = cls_axis(cp.kp, cp.d);
-          if constexpr (cp.d == 2) {
-            dcur = p ? nb[cp.kp] - cur[cp.kp] : cur[cp.kp] - nb[cp.kp];
-          } else {
-            const int s = p ? 1 : -1;
-            const T v = (cp.d == 0) ? val(std::integral_constant<int, cp.kp>{}, x + s, y, z)
-                                    : val(std::integral_constant<int, cp.kp>{}, x, y + s, z);
-            dcur = p ? v - cur[cp.kp] : cur[cp.kp] - v;
-          }
-        }
-        acc[cp.k] = fmadd<T>(T(cp.c), dcur, acc[cp.k]);
-      });
-
-      sfor<NC>([&](auto Kc) {
-        constexpr int K = decltype(Kc)::value;
-        const int idx = index_of(Kc, x, y, z);
-        if (idx >= 0 && (!per || (x < a.nx && y < a.ny))) {
-          constexpr int c = cls_id(K);
-          const T dg = fmadd<T>(T(a.omg[band_of(K)]), css[c], csa[c]);
-          T out = fmadd<T>(tinvh, acc[K], dg * cur[K]);
-          if constexpr (MODE == M_RESID) {
-            const T q = T(RHS[idx]);
-            out = q - out;
-            nrm1 += double(q) * double(q);
-          }
-          Y[idx] = TO(out);
-          nrm0 += double(out) * double(out);
-          if constexpr (MODE == M_APPLY) {
-            if (Y2 != nullptr) Y2[idx] = TO(out);
-          }
-          if constexpr (MODE == M_TRANSR) {
-            Y2[idx] = TO(cur[K]);
-            nrm1 += double(cur[K]) * double(cur[K]);
+      // Rows one staggering class at a time: form each (input, axis)
+      // difference once, fan it out to the rows of the class, store them.
+      const bool okz0 = PER || z < a.nz;
+      sfor<8>([&](auto Cc) {
+        constexpr int c = decltype(Cc)::value;
+        if constexpr (TB::class_has_rows(c)) {
+#ifdef PN_CLASS_BARRIER
+          // keep each class group's loads from being hoisted above the previous
+          // group (bounds the live registers)
+          __builtin_amdgcn_sched_barrier(0);
+#endif
+          constexpr int ib = TB::class_begin(c);
+          constexpr int ie = TB::class_end(c);
+          T acc[NC];
+          sfor<NC>([&](auto Kc) {
+            constexpr int K = decltype(Kc)::value;
+            if constexpr (cls_id(K) == c) acc[K] = T(0);
+          });
+          T dcur = T(0);
+          sfor<ie - ib>([&](auto Ic) {
+            constexpr int I = ib + decltype(Ic)::value;
+            constexpr Coupling cp = TB::cpl.v[I];
+            constexpr bool first = (I == ib) || TB::cpl.v[I - 1].kp != cp.kp || TB::cpl.v[I - 1].d != cp.d;
+            if constexpr (first) {
+              constexpr int p = cls_axis(cp.kp, cp.d);
+              if constexpr (cp.d == 2) {
+                dcur = p ? nb[cp.kp] - cur[cp.kp] : cur[cp.kp] - nb[cp.kp];
+              } else {
+                const unsigned lo = (cp.d == 0) ? (p ? oxp : oxm) : (p ? oyp : oym);
+                const T v = load(std::integral_constant<int, cp.kp>{}, zo, lo);
+                dcur = p ? v - cur[cp.kp] : cur[cp.kp] - v;
+              }
+            }
+            acc[cp.k] = fmadd<T>(T(cp.c), dcur, acc[cp.k]);
+          });
+          constexpr int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+          const bool ok = act && (cx || okx0) && (cy || oky0) && (cz || okz0);
+          if (ok) {
+            // squares summed per class in T, promoted to FP64 once per class
+            T cn0 = T(0), cn1 = T(0);
+            sfor<NC>([&](auto Kc) {
+              constexpr int K = decltype(Kc)::value;
+              if constexpr (cls_id(K) == c) {
+                const long long base = (long long)K * cs + zo;
+                const T dg = fmadd<T>(T(a.omg[band_of(K)]), css[c], csa[c]);
+                T out = fmadd<T>(tinvh, acc[K], dg * cur[K]);
+                if constexpr (MODE == M_RESID) {
+                  const T q = T(ldb(RHS + base, orhs));
+                  out = q - out;
+                  cn1 = fmadd<T>(q, q, cn1);
+                }
+                stb(Y + base, oo, TO(out));
+                if constexpr (NORM) cn0 = fmadd<T>(out, out, cn0);
+                if constexpr (MODE == M_TRANSR) {
+                  stb(Y2 + base, oo, TO(cur[K]));
+                  cn1 = fmadd<T>(cur[K], cur[K], cn1);
+                }
+              }
+            });
+            if constexpr (NORM) nrm0 += double(cn0);
+            if constexpr (MODE != M_APPLY) nrm1 += double(cn1);
           }
         }
       });
 #pragma unroll
-      for (int q = 0; q < 4; ++q) mprev[q] = mcur[q];
+      for (int q = 0; q < 4; ++q) { msa[q] = msa[4 + q]; mss[q] = mss[4 + q]; }
     }
   }
 
-  if (a.partials != nullptr) {
+  if constexpr (NORM) {
     block_sum2(nrm0, nrm1);
     if (threadIdx.x == 0) {
       a.partials[2 * L] = nrm0;
@@ -318,7 +387,7 @@ __device__ __forceinline__ void grid_sum2(const double* __restrict__ p, int n, d
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
 
 // After q = A p:  alpha = gamma / ||q||^2.
-__global__ void __launch_bounds__(kBlock) k_fin_alpha(DevState* st, const double* partials, int n) {
+static __global__ void __launch_bounds__(kBlock) k_fin_alpha(DevState* st, const double* partials, int n) {
   if (st->done) return;
   if (st->stop) {
     if (threadIdx.x == 0) st->done = 1;
@@ -340,7 +409,7 @@ __global__ void __launch_bounds__(kBlock) k_fin_alpha(DevState* st, const double
 }
 
 // After s = A^T r':  beta = ||s||^2 / gamma, convergence test on ||r'||^2.
-__global__ void __launch_bounds__(kBlock) k_fin_beta(DevState* st, const double* partials, int n) {
+static __global__ void __launch_bounds__(kBlock) k_fin_beta(DevState* st, const double* partials, int n) {
   if (st->done) return;
   double ss, rr;
   grid_sum2(partials, n, ss, rr);
@@ -356,7 +425,7 @@ __global__ void __launch_bounds__(kBlock) k_fin_beta(DevState* st, const double*
 }
 
 // After s = A^T r0, p = s:  start of an inner solve.
-__global__ void __launch_bounds__(kBlock) k_fin_init(DevState* st, const double* partials, int n, double inner_tol2) {
+static __global__ void __launch_bounds__(kBlock) k_fin_init(DevState* st, const double* partials, int n, double inner_tol2) {
   double ss, unused;
   grid_sum2(partials, n, ss, unused);
   if (threadIdx.x == 0) {
@@ -372,7 +441,7 @@ __global__ void __launch_bounds__(kBlock) k_fin_init(DevState* st, const double*
 }
 
 // After r = Q - A x (FP64):  true residual and ||Q||^2.
-__global__ void __launch_bounds__(kBlock) k_fin_resid(DevState* st, const double* partials, int n) {
+static __global__ void __launch_bounds__(kBlock) k_fin_resid(DevState* st, const double* partials, int n) {
   double rr, bb;
   grid_sum2(partials, n, rr, bb);
   if (threadIdx.x == 0) {
@@ -426,27 +495,70 @@ __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ v, long n, T va
 
 // x64 += d (refinement update)
 template <typename TD>
-__global__ void __launch_bounds__(kBlock) k_add_to64(double* __restrict__ x, const TD* __restrict__ d, long n) {
+__global__ void __launch_bounds__(kBlock) k_axpy64(double* __restrict__ x, const TD* __restrict__ d, long n) {
   const long stride = (long)gridDim.x * kBlock;
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) x[i] += double(d[i]);
 }
 
-// Thresholds sigma_t, packs (sigma_t, albedo) per cell, flags NaN / Inf.
-__global__ void __launch_bounds__(kBlock) k_medium_prep(const float* __restrict__ sigma_t,
+// Padded cell arrays: med32 = (sigma_a, sigma_s) in FP32 and med = (sigma_t,
+// albedo) with sigma_t raised to the threshold; the one-cell halo holds
+// clamped (vacuum) or wrapped (periodic) copies.  Flags NaN / Inf.
+static __global__ void __launch_bounds__(kBlock) k_medium_prep(const float* __restrict__ sigma_t,
                                                         const float* __restrict__ albedo, float thr,
-                                                        float2* __restrict__ out, long n, int* bad) {
-  const long stride = (long)gridDim.x * kBlock;
+                                                        int nx, int ny, int nz, int periodic,
+                                                        float2* __restrict__ med32, float2* __restrict__ med,
+                                                        int* bad) {
+  const long long CX = nx + 2, CY = ny + 2, n = CX * CY * (nz + 2);
+  const long long stride = (long long)gridDim.x * kBlock;
   int b = 0;
-  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    const float s = sigma_t[i], al = albedo[i];
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    int px = (int)(i % CX) - 1, py = (int)((i / CX) % CY) - 1, pz = (int)(i / (CX * CY)) - 1;
+    if (periodic) {
+      px = wrapi(px, nx); py = wrapi(py, ny); pz = wrapi(pz, nz);
+    } else {
+      px = min(max(px, 0), nx - 1); py = min(max(py, 0), ny - 1); pz = min(max(pz, 0), nz - 1);
+    }
+    const long long src = ((long long)pz * ny + py) * nx + px;
+    const float s = sigma_t[src], al = albedo[src];
     if (!isfinite(s) || !isfinite(al)) b = 1;
-    out[i] = make_float2(fmaxf(s, thr), al);
+    const float st = fmaxf(s, thr);
+    med[i] = make_float2(st, al);
+    med32[i] = make_float2(st * (1.0f - al), st * al);
   }
   if (b) atomicOr(bad, 1);
 }
 
+// Layout conversion between the packed API layout (coefficient k contiguous
+// over its class extent) and the padded lattice.  One grid row per k.
+struct PackArgs {
+  int nc;
+  int PX, PY, plane;
+  long long cs;
+  long long off[kMaxCoeff];
+  int ex[kMaxCoeff], ey[kMaxCoeff], ez[kMaxCoeff];
+};
+
+// DIR 0: padded[k] <- packed;  DIR 1: packed <- padded;  DIR 2: packed += padded
+template <typename TS, typename TD, int DIR>
+__global__ void __launch_bounds__(kBlock) k_pack(const TS* __restrict__ src, TD* __restrict__ dst, const PackArgs p) {
+  const int k = blockIdx.y;
+  const int ex = p.ex[k], ey = p.ey[k];
+  const long long sz = (long long)ex * ey * p.ez[k];
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < sz; i += stride) {
+    const int x = (int)(i % ex);
+    const long long t = i / ex;
+    const int y = (int)(t % ey), z = (int)(t / ey);
+    const long long pi = (long long)k * p.cs + ((long long)(z + 1) * p.PY + (y + 1)) * p.PX + (x + 1);
+    const long long qi = p.off[k] + i;
+    if constexpr (DIR == 0) dst[pi] = TD(src[qi]);
+    else if constexpr (DIR == 1) dst[qi] = TD(src[pi]);
+    else dst[qi] += TD(src[pi]);
+  }
+}
+
 // Flags NaN / Inf in a float vector.
-__global__ void __launch_bounds__(kBlock) k_check_finite(const float* __restrict__ v, long n, int* bad) {
+static __global__ void __launch_bounds__(kBlock) k_check_finite(const float* __restrict__ v, long n, int* bad) {
   const long stride = (long)gridDim.x * kBlock;
   int b = 0;
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)

@@ -1,0 +1,45 @@
+// Launch of the stencil kernel variants of one order.  Each order is
+// instantiated in its own translation unit (pn_order_N.hip) so the library
+// builds in parallel.
+#pragma once
+#include "pn_kernels.h"
+
+namespace pn {
+
+// Kernel flavours used by the library: (vector type, mode, output type).
+enum Kind {
+  K_F32_APPLY = 0,   // float  -> float  y = op(x)
+  K_F32_TRANSR = 1,  // float  -> float  r' = r - alpha q, y = A^T r'
+  K_F64_APPLY = 2,   // double -> double
+  K_F64_TRANSR = 3,  // double -> double
+  K_F64_RESID32 = 4, // double x, float Q -> float r = Q - A x
+  K_F64_RESID64 = 5  // double x, float Q -> double r
+};
+
+template <int N, typename T, int MODE, typename TO>
+hipError_t launch_flavour(bool per, bool norm, const StencilArgs& a, hipStream_t s) {
+  dim3 grid(a.nblocks), block(kBlock);
+  if (MODE == M_APPLY && !norm) {
+    if (per) hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, false, false>), grid, block, 0, s, a);
+  } else {
+    if (per) hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, false, true>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_order(int kind, bool per, bool norm, const StencilArgs& a, hipStream_t s) {
+  switch (kind) {
+    case K_F32_APPLY: return launch_flavour<N, float, M_APPLY, float>(per, norm, a, s);
+    case K_F32_TRANSR: return launch_flavour<N, float, M_TRANSR, float>(per, true, a, s);
+    case K_F64_APPLY: return launch_flavour<N, double, M_APPLY, double>(per, norm, a, s);
+    case K_F64_TRANSR: return launch_flavour<N, double, M_TRANSR, double>(per, true, a, s);
+    case K_F64_RESID32: return launch_flavour<N, double, M_RESID, float>(per, true, a, s);
+    case K_F64_RESID64: return launch_flavour<N, double, M_RESID, double>(per, true, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pn

@@ -67,6 +67,7 @@ struct Coupling {
   int d;     // derivative axis 0 = x, 1 = y, 2 = z
   int kp;    // input (column) coefficient
   double c;  // int omega_d Y^k Y^kp
+  int ck;    // staggering class id of k
 };
 
 struct Term { int d, lp, mp; double c; };
@@ -132,8 +133,17 @@ struct Table {
   struct Arr { Coupling v[NCPL]; };
   struct Need { bool v[NC][3]; };
 
-  // Couplings sorted by (kp, d, k): grouped by input coefficient and axis so a
-  // kernel can form each difference once and fan it out to its rows.
+  // Couplings sorted by (class of k, d, kp, k).  Along axis d the rows of
+  // class c read only inputs of class c ^ (1 << d), so every (kp, d)
+  // difference belongs to exactly one row class: a kernel can walk the row
+  // classes one at a time, form each difference once, fan it out to the rows
+  // of that class and retire their accumulators before the next class.
+  static constexpr bool before(const Coupling& a, const Coupling& b) {
+    if (a.ck != b.ck) return a.ck < b.ck;
+    if (a.d != b.d) return a.d < b.d;
+    if (a.kp != b.kp) return a.kp < b.kp;
+    return a.k < b.k;
+  }
   static constexpr Arr make() {
     Arr a{};
     int n = 0;
@@ -146,14 +156,14 @@ struct Table {
           a.v[n].d = t[i].d;
           a.v[n].kp = coeff_index(t[i].lp, t[i].mp);
           a.v[n].c = t[i].c;
+          a.v[n].ck = cls_id(a.v[n].k);
           ++n;
         }
       }
-    for (int i = 1; i < NCPL; ++i) {  // insertion sort by (kp, d, k)
+    for (int i = 1; i < NCPL; ++i) {  // insertion sort
       Coupling x = a.v[i];
       int j = i - 1;
-      while (j >= 0 && (a.v[j].kp > x.kp || (a.v[j].kp == x.kp && (a.v[j].d > x.d ||
-                                                 (a.v[j].d == x.d && a.v[j].k > x.k))))) {
+      while (j >= 0 && before(x, a.v[j])) {
         a.v[j + 1] = a.v[j];
         --j;
       }
@@ -161,7 +171,25 @@ struct Table {
     }
     return a;
   }
+  // first / one-past-last coupling index of row class c
   static constexpr Arr cpl = make();
+
+  struct Ranges { int b[9]; bool rows[8]; };
+  static constexpr Ranges make_ranges() {
+    Ranges r{};
+    for (int c = 0; c <= 8; ++c) {
+      int i = 0;
+      while (i < NCPL && cpl.v[i].ck < c) ++i;
+      r.b[c] = i;
+    }
+    for (int k = 0; k < NC; ++k) r.rows[cls_id(k)] = true;
+    return r;
+  }
+  static constexpr Ranges ranges = make_ranges();
+  // first / one-past-last coupling index of row class c; does class c hold rows
+  static constexpr int class_begin(int c) { return ranges.b[c]; }
+  static constexpr int class_end(int c) { return ranges.b[c + 1]; }
+  static constexpr bool class_has_rows(int c) { return ranges.rows[c]; }
 
   static constexpr Need make_need() {
     Need q{};

@@ -106,6 +106,12 @@ class Solver:
                                            _ptr(r, torch.float64) if r is not None else None, C.byref(rel)))
         return rel.value
 
+    def bench_apply(self, iters=20, transpose=False):
+        """Mean milliseconds of one in-loop FP32 apply (HIP events)."""
+        ms = C.c_double()
+        self._check(self.lib.pn_bench_apply(self.ctx, int(iters), int(transpose), C.byref(ms)))
+        return ms.value
+
     def set_zchunk(self, z):
         self._check(self.lib.pn_set_zchunk(self.ctx, int(z)))
 

@@ -13,7 +13,7 @@ import torch
 
 from oracle.apply import Operator, rows_of
 from oracle.assemble import assemble, rhs_isotropic
-from oracle.solve import direct
+from oracle.solve import cgls, direct
 from synth import (config_p1_homogeneous, config_p3_fbm, config_p5_nebula, config_small,
                    config_uniform_periodic)
 
@@ -137,14 +137,25 @@ def test_residual64_vs_oracle():
     ref = b.astype(np.float64) - A @ x
     bound = 64 * EPS64 * (np.abs(b) + magnitude_matrix(m) @ np.abs(x))
     assert np.all(np.abs(r.cpu().numpy() - ref) <= bound)
-    assert abs(rel - np.linalg.norm(ref) / np.linalg.norm(b)) < 1e-12 * rel
+    assert abs(rel - np.linalg.norm(ref) / np.linalg.norm(b.astype(np.float64))) < 1e-12 * rel
     s.close()
+
+
+def oracle_solution(A, b):
+    """Reference solution: SuperLU for small systems, the oracle's FP64 CGLS
+    to a relative residual of 1e-13 otherwise (3D fill-in makes LU slow)."""
+    if A.shape[0] <= 20000:
+        return direct(A, b)
+    AT = A.T.tocsr()
+    u, info = cgls(lambda v: A @ v, lambda v: AT @ v, b, tol=1e-13)
+    assert info["rel_residual"] <= 1e-12
+    return u
 
 
 def _solve_and_check(m, tol, precision, err_tol=1e-5, **kw):
     A, lay = oracle_matrix(m)
     b = rhs_isotropic(lay, m.q00[0])
-    u = direct(A, b)
+    u = oracle_solution(A, b)
     s = make_solver(m)
     rhs = s.rhs_from_q00(dev(m.q00[0]))
     assert np.array_equal(rhs.cpu().numpy(), b.astype(np.float32))
