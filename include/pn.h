@@ -98,7 +98,17 @@ typedef struct {
   double inner_tol;   /* relative reduction of the inner FP32 residual         */
   int use_guess;      /* 0: start from x = 0; 1: start from the x passed in    */
   int graph_iters;    /* Krylov iterations per captured HIP graph launch       */
+  int variant;        /* PN_VARIANT_AUTO or PN_VARIANT_CGLS (see pn_solve)     */
 } pn_solve_opts;
+
+/* Krylov variant of the FP32 inner solve.  AUTO and CGLS: the residual-based
+ * CGLS form (r <- r - alpha q fused into s = A^T r).  CG: CG on the normal
+ * equations A^T A u = A^T Q with the recursive normal residual
+ * (s <- s - alpha A^T q, ||r||^2 <- ||r||^2 - alpha gamma; 10 vector passes
+ * per iteration); needs the LDS-tiled stencil (pn_set_tiles), else CGLS. */
+#define PN_VARIANT_AUTO 0
+#define PN_VARIANT_CGLS 1
+#define PN_VARIANT_CG 2
 
 #define PN_MAX_HISTORY 64
 typedef struct {
@@ -173,6 +183,16 @@ pn_status pn_bench_apply(pn_ctx* ctx, int iters, int transpose, double* ms_per_a
  * (0 = automatic).  Results do not depend on it (bitwise). */
 pn_status pn_set_zchunk(pn_ctx* ctx, int zchunk);
 int pn_get_zchunk(const pn_ctx* ctx);
+
+/* Opt-in LDS-tiled FP32 stencil (vacuum boundary): a block owns a tx x ty
+ * tile of (x, y) columns and zchunk planes (0 = automatic); pn_apply and the
+ * CG variant then use it.  tx = ty = 0 switches back to the register-window
+ * stencil (the default).  Fails with PN_ERR_ARG for shapes that do not fit
+ * (at most 256 threads, the tile's one-point border no larger than the
+ * block, LDS within the device limit).  pn_get_tiles reports the current
+ * shape (tx = ty = 0 when the tiled stencil is not in use). */
+pn_status pn_set_tiles(pn_ctx* ctx, int tx, int ty, int zchunk);
+pn_status pn_get_tiles(const pn_ctx* ctx, int* tx, int* ty, int* zchunk);
 
 /* Coupling table compiled into the library for `order`: writes up to `cap`
  * entries (row k, axis d, column k', value int omega_d Y^k Y^k') into the

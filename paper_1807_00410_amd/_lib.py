@@ -39,7 +39,8 @@ class PnLayout(C.Structure):
 
 class PnSolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("max_iter", C.c_int), ("max_refine", C.c_int),
-                ("inner_tol", C.c_double), ("use_guess", C.c_int), ("graph_iters", C.c_int)]
+                ("inner_tol", C.c_double), ("use_guess", C.c_int), ("graph_iters", C.c_int),
+                ("variant", C.c_int)]
 
 
 class PnSolveInfo(C.Structure):
@@ -65,6 +66,8 @@ SIGNATURES = [
     ("pn_bench_apply", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     ("pn_set_zchunk", C.c_int, [C.c_void_p, C.c_int]),
     ("pn_get_zchunk", C.c_int, [C.c_void_p]),
+    ("pn_set_tiles", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    ("pn_get_tiles", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("pn_coupling_table", C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                     C.POINTER(C.c_double), C.c_int]),
 ]

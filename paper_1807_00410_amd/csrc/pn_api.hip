@@ -3,6 +3,7 @@
 // argument conventions in include/pn.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -21,6 +22,20 @@ extern template hipError_t launch_order<4>(int, bool, bool, const StencilArgs&, 
 extern template hipError_t launch_order<5>(int, bool, bool, const StencilArgs&, hipStream_t);
 extern template hipError_t launch_order<6>(int, bool, bool, const StencilArgs&, hipStream_t);
 extern template hipError_t launch_order<7>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<1>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<2>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<3>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<4>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<5>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<6>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<7>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t lds_prepare<1>(size_t);
+extern template hipError_t lds_prepare<2>(size_t);
+extern template hipError_t lds_prepare<3>(size_t);
+extern template hipError_t lds_prepare<4>(size_t);
+extern template hipError_t lds_prepare<5>(size_t);
+extern template hipError_t lds_prepare<6>(size_t);
+extern template hipError_t lds_prepare<7>(size_t);
 }  // namespace pn
 
 using namespace pn;
@@ -65,8 +80,92 @@ struct pn_ctx {
   // captured inner iterations
   hipGraphExec_t gexec32 = nullptr, gexec64 = nullptr;
   int giters32 = 0, giters64 = 0;
+  // LDS-tiled FP32 stencil (vacuum boundary): tile shape and z chunking
+  int lds_ok = 0;   // the tiled kernel fits this context
+  int use_lds = 0;  // applies and the CG variant use it (opt-in, pn_set_tiles)
+  int TX = 0, TY = 0, ntx = 0, nty = 0, lzchunk = 0, lnzc = 0, lnblocks = 0;
+  size_t lds_bytes = 0, lds_max = 0;
+  hipGraphExec_t gexec_cg = nullptr;  // captured CG-on-normal-equations iterations
+  int giters_cg = 0;
   std::string err;
 };
+
+static constexpr size_t kLdsMax = 160 * 1024;
+
+// Tile geometry of the LDS kernel; returns false if the shape is not usable.
+static bool set_tiles(pn_ctx* c, int TX, int TY, int zchunk) {
+  if (c->bc != PN_BC_VACUUM || TX < 1 || TY < 1) return false;
+  const int threads = ((TX * TY + 63) / 64) * 64;
+  if (threads > kBlock || 2 * (TX + 2) + 2 * TY > threads) return false;
+  const size_t bytes = sizeof(float) * (size_t)c->nc * (TX + 2) * (TY + 2);
+  if (bytes > c->lds_max) return false;
+  const int ntx = (c->Ex + TX - 1) / TX, nty = (c->Ey + TY - 1) / TY;
+  if (zchunk <= 0) {  // about 8 blocks per CU, at least 4 planes per chunk
+    const int nzc = (2048 + ntx * nty - 1) / (ntx * nty);
+    zchunk = (c->Ez + nzc - 1) / nzc;
+    if (zchunk < 4) zchunk = 4;
+  }
+  if (zchunk > c->Ez) zchunk = c->Ez;
+  const int lnzc = (c->Ez + zchunk - 1) / zchunk;
+  if ((long long)ntx * nty * lnzc > c->max_blocks) return false;
+  c->TX = TX; c->TY = TY; c->ntx = ntx; c->nty = nty;
+  c->lzchunk = zchunk; c->lnzc = lnzc; c->lnblocks = ntx * nty * lnzc;
+  c->lds_bytes = bytes;
+  return true;
+}
+
+// Default tile: least lanes per lattice column (idle lanes and halo reloads
+// weighted), rows of at least 32 columns for coalescing, and preferring shapes
+// whose LDS lets two blocks share a CU.
+static void choose_tiles(pn_ctx* c) {
+  double best = 1e30;
+  int bx = 0, by = 0;
+  const int txmin = c->Ex < 32 ? c->Ex : 32;
+  for (int TX = txmin; TX <= (c->Ex < kBlock ? c->Ex : kBlock); ++TX)
+    for (int TY = 1; TX * TY <= kBlock; ++TY) {
+      const int threads = ((TX * TY + 63) / 64) * 64;
+      if (2 * (TX + 2) + 2 * TY > threads) continue;
+      const size_t bytes = sizeof(float) * (size_t)c->nc * (TX + 2) * (TY + 2);
+      if (bytes > c->lds_max) continue;
+      const double lanes = (double)((c->Ex + TX - 1) / TX) * ((c->Ey + TY - 1) / TY) * threads;
+      const double waste = lanes / ((double)c->Ex * c->Ey);
+      const double halo = (double)((TX + 2) * (TY + 2) - TX * TY) / (TX * TY);
+      const double cost = waste * (1.0 + 0.25 * halo) * (2 * bytes <= kLdsMax ? 1.0 : 1.15);
+      if (cost < best) { best = cost; bx = TX; by = TY; }
+    }
+  c->lds_ok = (bx > 0) && set_tiles(c, bx, by, 0);
+}
+
+static StencilArgs base_args(const pn_ctx* c);
+
+// LDS-tiled FP32 apply: mode M_APPLY (norm optional) or M_SUPD.
+static hipError_t launch_lds(const pn_ctx* c, int mode, bool norm, StencilArgs a, hipStream_t s) {
+  a.TX = c->TX; a.TY = c->TY; a.ntx = c->ntx; a.nty = c->nty;
+  a.zchunk = c->lzchunk; a.nzc = c->lnzc; a.nblocks = c->lnblocks;
+  switch (c->order) {
+    case 1: return launch_lds_order<1>(mode, norm, a, s);
+    case 2: return launch_lds_order<2>(mode, norm, a, s);
+    case 3: return launch_lds_order<3>(mode, norm, a, s);
+    case 4: return launch_lds_order<4>(mode, norm, a, s);
+    case 5: return launch_lds_order<5>(mode, norm, a, s);
+    case 6: return launch_lds_order<6>(mode, norm, a, s);
+    case 7: return launch_lds_order<7>(mode, norm, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t lds_prepare_order(int order, size_t bytes) {
+  switch (order) {
+    case 1: return lds_prepare<1>(bytes);
+    case 2: return lds_prepare<2>(bytes);
+    case 3: return lds_prepare<3>(bytes);
+    case 4: return lds_prepare<4>(bytes);
+    case 5: return lds_prepare<5>(bytes);
+    case 6: return lds_prepare<6>(bytes);
+    case 7: return lds_prepare<7>(bytes);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 // ------------------------------------------------------------ utilities --
 #define PN_HIP(call)                                                              \
@@ -184,6 +283,7 @@ static void free_all(pn_ctx* c) {
   if (!c) return;
   if (c->gexec32) hipGraphExecDestroy(c->gexec32);
   if (c->gexec64) hipGraphExecDestroy(c->gexec64);
+  if (c->gexec_cg) hipGraphExecDestroy(c->gexec_cg);
   hipFree(c->med); hipFree(c->med32);
   for (int i = 0; i < 2; ++i) { hipFree(c->r32[i]); hipFree(c->r64[i]); }
   hipFree(c->s32); hipFree(c->p32); hipFree(c->q32); hipFree(c->d32); hipFree(c->b32); hipFree(c->x64);
@@ -220,6 +320,7 @@ extern "C" void pn_default_opts(pn_solve_opts* o) {
   o->inner_tol = 1e-3;
   o->use_guess = 0;
   o->graph_iters = 32;
+  o->variant = PN_VARIANT_AUTO;
 }
 
 extern "C" const char* pn_last_error(const pn_ctx* c) {
@@ -274,6 +375,10 @@ extern "C" pn_status pn_setup(int order, const pn_grid* grid, const pn_medium* m
   set_geometry(c, 0);
   c->max_blocks = 1 << 16;
   if (c->nblocks > c->max_blocks) { delete c; return fail(nullptr, PN_ERR_ARG, "grid too large in x*y"); }
+  if (c->nv >= (1LL << 31) - 1) {  // kernels use 32-bit element offsets
+    delete c;
+    return fail(nullptr, PN_ERR_ARG, "too many unknowns for the padded layout (>= 2^31)");
+  }
 
   auto bail = [&](pn_status s, const std::string& m) {
     free_all(c);
@@ -313,6 +418,21 @@ extern "C" pn_status pn_setup(int order, const pn_grid* grid, const pn_medium* m
   SETUP_HIP(hipMemcpyAsync(c->flag_host, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   SETUP_HIP(hipStreamSynchronize(c->stream));
   if (*c->flag_host) return bail(PN_ERR_NONFINITE, "medium contains NaN or Inf");
+  {
+    // LDS per block: 64 KiB by default; up to the device's opt-in limit when
+    // the kernel attribute can be raised.
+    int dev = 0, optin = 0;
+    c->lds_max = 64 * 1024 - 1024;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess &&
+        optin > 64 * 1024) {
+      const size_t want = std::min<size_t>(kLdsMax, (size_t)optin) - 1024;
+      if (lds_prepare_order(c->order, want) == hipSuccess) c->lds_max = want;
+      else (void)hipGetLastError();  // clear; keep the default limit
+    }
+    (void)hipGetLastError();
+  }
+  choose_tiles(c);
 #undef SETUP_HIP
   *out = c;
   return PN_OK;
@@ -325,6 +445,31 @@ extern "C" pn_status pn_set_zchunk(pn_ctx* c, int zchunk) {
   if (c->nblocks > c->max_blocks) { set_geometry(c, 0); return fail(c, PN_ERR_ARG, "too many blocks"); }
   if (c->gexec32) { hipGraphExecDestroy(c->gexec32); c->gexec32 = nullptr; c->giters32 = 0; }
   if (c->gexec64) { hipGraphExecDestroy(c->gexec64); c->gexec64 = nullptr; c->giters64 = 0; }
+  return PN_OK;
+}
+
+extern "C" pn_status pn_set_tiles(pn_ctx* c, int tx, int ty, int zchunk) {
+  if (!c) return PN_ERR_ARG;
+  if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
+  if (tx == 0 && ty == 0) {  // back to the register-window stencil
+    c->use_lds = 0;
+    return PN_OK;
+  }
+  if (!c->lds_ok) return fail(c, PN_ERR_ARG, "the LDS-tiled stencil is not available for this context");
+  const int otx = c->TX, oty = c->TY, oz = c->lzchunk;
+  if (!set_tiles(c, tx, ty, zchunk)) {
+    set_tiles(c, otx, oty, oz);
+    return fail(c, PN_ERR_ARG, "tile shape not usable");
+  }
+  c->use_lds = 1;
+  return PN_OK;
+}
+
+extern "C" pn_status pn_get_tiles(const pn_ctx* c, int* tx, int* ty, int* zchunk) {
+  if (!c || !tx || !ty || !zchunk) return PN_ERR_ARG;
+  *tx = c->use_lds ? c->TX : 0;
+  *ty = c->use_lds ? c->TY : 0;
+  *zchunk = c->use_lds ? c->lzchunk : c->zchunk;
   return PN_OK;
 }
 
@@ -363,7 +508,8 @@ extern "C" pn_status pn_apply(pn_ctx* c, const float* x, float* y, int transpose
   StencilArgs a = base_args(c);
   a.tsign = transpose ? -1.0 : 1.0;
   a.x = c->p32; a.y = c->q32;
-  PN_HIP((launch_stencil<float, M_APPLY, float>(c, a, c->stream)));
+  if (c->use_lds) PN_HIP(launch_lds(c, M_APPLY, false, a, c->stream));
+  else PN_HIP((launch_stencil<float, M_APPLY, float>(c, a, c->stream)));
   PN_HIP((launch_pack<float, float, 1>(c, c->q32, y, c->stream)));
   return PN_OK;
 }
@@ -393,9 +539,13 @@ extern "C" pn_status pn_bench_apply(pn_ctx* c, int iters, int transpose, double*
   StencilArgs a = base_args(c);
   a.tsign = transpose ? -1.0 : 1.0;
   a.x = c->p32; a.y = c->q32;
-  PN_HIP((launch_stencil<float, M_APPLY, float>(c, a, c->stream)));  // warm-up
+  auto one = [&]() -> hipError_t {
+    return c->use_lds ? launch_lds(c, M_APPLY, false, a, c->stream)
+                     : launch_stencil<float, M_APPLY, float>(c, a, c->stream);
+  };
+  PN_HIP(one());  // warm-up
   PN_HIP(hipEventRecord(e0, c->stream));
-  for (int i = 0; i < iters; ++i) PN_HIP((launch_stencil<float, M_APPLY, float>(c, a, c->stream)));
+  for (int i = 0; i < iters; ++i) PN_HIP(one());
   PN_HIP(hipEventRecord(e1, c->stream));
   PN_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -453,6 +603,40 @@ static hipError_t enqueue_iteration(pn_ctx* c, T* d, T* p, T* q, T* s, const T* 
   return hipGetLastError();
 }
 
+// One iteration of CG on the normal equations (FP32 vectors, LDS-tiled stencil):
+// q = A p | alpha | s -= alpha A^T q | beta | x += alpha p, p = s + beta p.
+static hipError_t enqueue_iteration_cg(pn_ctx* c, float* d, float* p, float* q, float* s, hipStream_t st) {
+  StencilArgs a = base_args(c);
+  a.st = c->st;
+  a.partials = c->partials;
+  a.x = p; a.y = q; a.tsign = 1.0;
+  hipError_t e = launch_lds(c, M_APPLY, true, a, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fin_alpha_cg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->lnblocks);
+  a.x = q; a.y = s; a.tsign = -1.0;
+  e = launch_lds(c, M_SUPD, true, a, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fin_beta_cg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->lnblocks);
+  hipLaunchKernelGGL((k_update_xp<float>), dim3(grid_for(c->nv / 4 + 1)), dim3(kBlock), 0, st, d, p,
+                     (const float*)s, (long)c->nv, (const DevState*)c->st);
+  return hipGetLastError();
+}
+
+static pn_status build_graph_cg(pn_ctx* c, int iters, hipGraphExec_t* exec) {
+  hipGraph_t g = nullptr;
+  PN_HIP(hipStreamBeginCapture(c->sstream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < iters && e == hipSuccess; ++i)
+    e = enqueue_iteration_cg(c, c->d32, c->p32, c->q32, c->s32, c->sstream);
+  hipError_t e2 = hipStreamEndCapture(c->sstream, &g);
+  if (e != hipSuccess) { if (g) hipGraphDestroy(g); return fail(c, PN_ERR_HIP, std::string("capture: ") + hipGetErrorString(e)); }
+  if (e2 != hipSuccess) return fail(c, PN_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
+  hipError_t e3 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e3 != hipSuccess) return fail(c, PN_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e3));
+  return PN_OK;
+}
+
 template <typename T>
 static pn_status build_graph(pn_ctx* c, int iters, T* d, T* p, T* q, T* s, T* r0, T* r1,
                              hipGraphExec_t* exec) {
@@ -487,10 +671,18 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     r0 = c->r64[0]; r1 = c->r64[1]; s = c->s64; p = c->p64; q = c->q64; d = c->d64;
     gexec = &c->gexec64; giters = &c->giters64;
   }
+  // FP32 with the LDS-tiled stencil: CG on the normal equations with the
+  // recursive normal residual (10 vector passes per iteration); otherwise
+  // CGLS with the recursive residual r (11 passes, r ping-pong).
+  const bool cg = (sizeof(T) == 4) && c->use_lds && o.variant == PN_VARIANT_CG;
+  if (cg) {
+    gexec = &c->gexec_cg;
+    giters = &c->giters_cg;
+  }
   int gi = o.graph_iters < 2 ? 2 : (o.graph_iters + 1) & ~1;  // even: r ends in r0
   if (*gexec == nullptr || *giters != gi) {
     if (*gexec) { hipGraphExecDestroy(*gexec); *gexec = nullptr; }
-    pn_status e = build_graph<T>(c, gi, d, p, q, s, r0, r1, gexec);
+    pn_status e = cg ? build_graph_cg(c, gi, gexec) : build_graph<T>(c, gi, d, p, q, s, r0, r1, gexec);
     if (e != PN_OK) return e;
     *giters = gi;
   }
@@ -532,8 +724,10 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, d, (long)c->nv, T(0));
     StencilArgs a = base_args(c);
     a.x = r0; a.y = s; a.tsign = -1.0; a.partials = c->partials;
-    PN_HIP((launch_stencil<T, M_APPLY, T>(c, a, ss)));
-    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials, c->nblocks, itol * itol);
+    if (cg) PN_HIP(launch_lds(c, M_APPLY, true, a, ss));
+    else PN_HIP((launch_stencil<T, M_APPLY, T>(c, a, ss)));
+    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials,
+                       cg ? c->lnblocks : c->nblocks, itol * itol);
     PN_HIP(hipGetLastError());
     PN_HIP(hipMemcpyAsync(p, s, sizeof(T) * c->nv, hipMemcpyDeviceToDevice, ss));  // p = s
     for (;;) {

@@ -55,7 +55,9 @@ struct DevState {
   int pad[3];
 };
 
-enum Mode { M_APPLY = 0, M_TRANSR = 1, M_RESID = 2 };
+// M_SUPD: s <- s - alpha * op(x) (the normal-equation residual update of CG
+// on A^T A), used by the LDS-tiled kernel.
+enum Mode { M_APPLY = 0, M_TRANSR = 1, M_RESID = 2, M_SUPD = 3 };
 
 // Internal vectors live on a padded lattice shared by every coefficient:
 // coefficient k occupies [k*cs, (k+1)*cs); lattice point (x, y, z) of any
@@ -85,6 +87,8 @@ struct StencilArgs {
   void* y2;            // M_TRANSR: updated r
   DevState* st;        // device scalars (alpha for M_TRANSR, stop/done flags), may be null
   double* partials;    // [nblocks][2] FP64 partial sums, may be null
+  // LDS-tiled kernel only: tile of TX x TY columns, ntx x nty tiles per plane
+  int TX, TY, ntx, nty;
 };
 
 template <class F, int... I>
@@ -140,7 +144,8 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double s0 = 0.0, s1 = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) { s0 += red[0][i]; s1 += red[1][i]; }
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) { s0 += red[0][i]; s1 += red[1][i]; }
     a = s0; b = s1;
   }
 }
@@ -217,9 +222,15 @@ __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil(const Stenci
     if constexpr (PER) z = wrapi(z, a.nz);
     return (long long)__builtin_amdgcn_readfirstlane((z + 1) * a.plane);
   };
+  // Element offset of (coefficient, plane) as an opaque uniform 32-bit value:
+  // recomputed with two scalar ops per use instead of ~36 loop-invariant 64-bit
+  // bases being hoisted out of the z loop and spilled into vector registers.
+  auto cbase = [&](int k, long long zo) -> long long {
+    return (long long)__builtin_amdgcn_readfirstlane((int)((long long)k * cs + zo));
+  };
   auto load = [&](auto KPc, long long zo, unsigned lo) -> T {
     constexpr int KP = decltype(KPc)::value;
-    const long long base = (long long)KP * cs + zo;
+    const long long base = cbase(KP, zo);
     if constexpr (MODE == M_TRANSR) return fmadd<T>(-alpha, ldb(X2 + base, lo), ldb(X + base, lo));
     else return ldb(X + base, lo);
   };
@@ -329,7 +340,7 @@ __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil(const Stenci
             sfor<NC>([&](auto Kc) {
               constexpr int K = decltype(Kc)::value;
               if constexpr (cls_id(K) == c) {
-                const long long base = (long long)K * cs + zo;
+                const long long base = cbase(K, zo);
                 const T dg = fmadd<T>(T(a.omg[band_of(K)]), css[c], csa[c]);
                 T out = fmadd<T>(tinvh, acc[K], dg * cur[K]);
                 if constexpr (MODE == M_RESID) {
@@ -437,6 +448,50 @@ static __global__ void __launch_bounds__(kBlock) k_fin_init(DevState* st, const 
     st->breakdown = 0;
     st->alpha = 0.0;
     st->beta = 0.0;
+  }
+}
+
+// CG on the normal equations with the recursive normal residual s
+// (q = A p;  alpha = gamma / ||q||^2;  s <- s - alpha A^T q;  x += alpha p;
+// p <- s + beta p).  The residual norm follows ||r'||^2 = ||r||^2 - alpha gamma
+// (r' = r - alpha q and <r, q> = <s, p> = gamma), so r itself is never formed.
+// After q = A p:
+static __global__ void __launch_bounds__(kBlock) k_fin_alpha_cg(DevState* st, const double* partials, int n) {
+  if (st->done) return;
+  if (st->stop) {
+    if (threadIdx.x == 0) st->done = 1;
+    return;
+  }
+  double qq, unused;
+  grid_sum2(partials, n, qq, unused);
+  if (threadIdx.x == 0) {
+    st->qq = qq;
+    if (!(qq > 0.0) || !finite_d(qq)) {
+      st->breakdown = 1;
+      st->alpha = 0.0;
+      st->stop = 1;
+      st->done = 1;
+    } else {
+      const double al = st->gamma / qq;
+      st->alpha = al;
+      st->rr -= al * st->gamma;
+      st->iters += 1;
+      if (st->rr <= st->tol2 || st->iters >= st->max_iters) st->stop = 1;
+    }
+  }
+}
+
+// After s <- s - alpha A^T q (partials hold ||s||^2):
+static __global__ void __launch_bounds__(kBlock) k_fin_beta_cg(DevState* st, const double* partials, int n) {
+  if (st->done || st->stop) return;
+  double ss, unused;
+  grid_sum2(partials, n, ss, unused);
+  if (threadIdx.x == 0) {
+    const double g0 = st->gamma;
+    st->beta = (g0 > 0.0) ? ss / g0 : 0.0;
+    st->gamma = ss;
+    if (!finite_d(ss)) { st->breakdown = 1; st->stop = 1; st->nonfinite = 1.0; }
+    if (!(ss > 0.0)) st->stop = 1;
   }
 }
 

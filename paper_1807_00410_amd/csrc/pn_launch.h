@@ -3,6 +3,7 @@
 // builds in parallel.
 #pragma once
 #include "pn_kernels.h"
+#include "pn_stencil_lds.h"
 
 namespace pn {
 

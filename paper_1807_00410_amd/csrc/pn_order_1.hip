@@ -1,6 +1,8 @@
-// Stencil kernels of order 1 (see pn_launch.h).
+// Stencil kernels of order 1 (see pn_launch.h and pn_stencil_lds.h).
 #include "pn_launch.h"
 
 namespace pn {
 template hipError_t launch_order<1>(int, bool, bool, const StencilArgs&, hipStream_t);
+template hipError_t launch_lds_order<1>(int, bool, const StencilArgs&, hipStream_t);
+template hipError_t lds_prepare<1>(size_t);
 }  // namespace pn

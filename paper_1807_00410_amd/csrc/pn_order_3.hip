@@ -1,6 +1,8 @@
-// Stencil kernels of order 3 (see pn_launch.h).
+// Stencil kernels of order 3 (see pn_launch.h and pn_stencil_lds.h).
 #include "pn_launch.h"
 
 namespace pn {
 template hipError_t launch_order<3>(int, bool, bool, const StencilArgs&, hipStream_t);
+template hipError_t launch_lds_order<3>(int, bool, const StencilArgs&, hipStream_t);
+template hipError_t lds_prepare<3>(size_t);
 }  // namespace pn

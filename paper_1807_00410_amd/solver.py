@@ -118,8 +118,16 @@ class Solver:
     def zchunk(self):
         return self.lib.pn_get_zchunk(self.ctx)
 
+    def set_tiles(self, tx, ty, zchunk=0):
+        self._check(self.lib.pn_set_tiles(self.ctx, int(tx), int(ty), int(zchunk)))
+
+    def tiles(self):
+        tx, ty, z = C.c_int(), C.c_int(), C.c_int()
+        self._check(self.lib.pn_get_tiles(self.ctx, C.byref(tx), C.byref(ty), C.byref(z)))
+        return tx.value, ty.value, z.value
+
     def solve(self, rhs, x=None, tol=1e-8, precision="fp32_ir", max_iter=200000, max_refine=40,
-              inner_tol=1e-3, use_guess=False, graph_iters=32, raise_on_fail=True):
+              inner_tol=1e-3, use_guess=False, graph_iters=32, variant="auto", raise_on_fail=True):
         """Solves A x = rhs.  Returns (x, info dict)."""
         if x is None:
             x = torch.zeros(self.n, dtype=torch.float64, device=rhs.device)
@@ -131,6 +139,7 @@ class Solver:
         opts.inner_tol = float(inner_tol)
         opts.use_guess = int(bool(use_guess))
         opts.graph_iters = int(graph_iters)
+        opts.variant = {"auto": 0, "cgls": 1, "cg": 2}[variant]
         info = L.PnSolveInfo()
         rc = self.lib.pn_solve(self.ctx, _ptr(rhs, torch.float32), _ptr(x, torch.float64), float(tol),
                                C.byref(opts), C.byref(info))
