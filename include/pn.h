@@ -199,6 +199,79 @@ pn_status pn_get_tiles(const pn_ctx* ctx, int* tx, int* ty, int* zchunk);
  * host arrays and returns the total count (-1 on bad arguments). */
 int pn_coupling_table(int order, int* k, int* d, int* kp, double* v, int cap);
 
+/* Launch autotuner: times the FP32 stencil apply of ctx for each candidate
+ * z-chunk (planes of z one thread block marches; the launch width against
+ * the window re-read at chunk borders) with `iters` timed launches each,
+ * keeps the fastest for ctx and records it in the process-wide tune cache
+ * under (order, nx, ny, nz, bc).  pn_setup and pn_batch_setup take the launch
+ * shape from that cache when it has an entry.  Writes the chosen z-chunk and
+ * its mean milliseconds per apply (either pointer may be NULL).  Results do
+ * not depend on the launch shape (bitwise).  Synchronous. */
+pn_status pn_autotune(pn_ctx* ctx, int iters, int* zchunk, double* ms_per_apply);
+
+/* The tune cache as a text file, one entry per line:
+ * "order nx ny nz bc zchunk ms" ('#' starts a comment line).  Load merges the
+ * file into the cache (PN_ERR_ARG on a missing file or a malformed line; the
+ * lines before it are kept). */
+pn_status pn_tune_cache_save(const char* path);
+pn_status pn_tune_cache_load(const char* path);
+int pn_tune_cache_size(void);
+void pn_tune_cache_clear(void);
+
+/* ------------------------------------------------------------------------
+ * Batched solve: many media of uneven grid size and order, each with nrhs
+ * right-hand sides (emission fields), solved together.  A system is one
+ * (problem p, right-hand side r) pair, index p * nrhs + r.  Each Krylov stage
+ * is one launch over all systems of an order (stencil) or over all systems
+ * (scalars, vectors), the iterations are captured in one HIP graph, and every
+ * system carries its own device-side scalars and convergence flags, so it
+ * stops on its own.  The right-hand sides of one problem share its A; their
+ * thread blocks for one tile run next to each other so the medium is fetched
+ * from memory once per tile.  Per system the arithmetic is that of pn_solve
+ * (FP32 CGLS, FP64 dot products and iterative refinement) with the same
+ * launch shape, so results match pn_solve on the same system bitwise.
+ * ---------------------------------------------------------------------- */
+typedef struct pn_batch pn_batch;
+
+typedef struct {
+  int order;          /* 1..7 */
+  pn_grid grid;
+  pn_medium medium;   /* copied at setup, as for pn_setup */
+} pn_problem;
+
+/* Builds the batch: per problem the medium and padded geometry, per system
+ * the Krylov workspace (7 FP32 vectors and one FP64 vector of the padded
+ * length, about 36 bytes per unknown).  tune != 0 runs the autotuner for every
+ * (order, grid, bc) not yet in the tune cache first.  On failure *out is NULL
+ * and pn_batch_last_error(NULL) tells why. */
+pn_status pn_batch_setup(int nprob, const pn_problem* probs, int nrhs, int tune, void* stream,
+                         pn_batch** out);
+
+/* Layout of problem `prob` (as pn_layout_query). */
+pn_status pn_batch_layout(const pn_batch* batch, int prob, pn_layout* layout);
+/* Launch z-chunk used for problem `prob` (-1 on bad arguments). */
+int pn_batch_zchunk(const pn_batch* batch, int prob);
+/* Total unknowns over all systems. */
+long long pn_batch_unknowns(const pn_batch* batch);
+
+/* Solves every system to ||Q - A x||_2 <= tol ||Q||_2.  rhs and x are HOST
+ * arrays of nprob * nrhs DEVICE pointers (packed layout of the system's
+ * problem; rhs FP32, x FP64 in/out as for pn_solve).  opts as for pn_solve;
+ * precision must be PN_FP32_IR.  info: NULL or a host array of nprob * nrhs
+ * entries, one per system (seconds = wall time of the whole batch).  Returns
+ * PN_OK when every system converged, else the status of the first system that
+ * did not (the others are still solved; see info).  Synchronous. */
+pn_status pn_batch_solve(pn_batch* batch, const float* const* rhs, double* const* x, double tol,
+                         const pn_solve_opts* opts, pn_solve_info* info);
+
+/* Times `iters` batched FP32 applies over every system (each system's
+ * direction vector into its product vector, as in the Krylov loop) with HIP
+ * events; writes the mean milliseconds per batched apply.  Synchronous. */
+pn_status pn_batch_bench_apply(pn_batch* batch, int iters, int transpose, double* ms_per_apply);
+
+void pn_batch_destroy(pn_batch* batch);
+const char* pn_batch_last_error(const pn_batch* batch);
+
 /* Frees the context and its workspace.  NULL is ignored. */
 void pn_destroy(pn_ctx* ctx);
 

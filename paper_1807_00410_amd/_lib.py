@@ -49,6 +49,10 @@ class PnSolveInfo(C.Structure):
                 ("nhistory", C.c_int), ("history", C.c_double * PN_MAX_HISTORY)]
 
 
+class PnProblem(C.Structure):
+    _fields_ = [("order", C.c_int), ("grid", PnGrid), ("medium", PnMedium)]
+
+
 # (name, restype, argtypes) of every exported symbol declared in include/pn.h
 SIGNATURES = [
     ("pn_abi_version", C.c_int, []),
@@ -70,6 +74,21 @@ SIGNATURES = [
     ("pn_get_tiles", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("pn_coupling_table", C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                     C.POINTER(C.c_double), C.c_int]),
+    ("pn_autotune", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    ("pn_tune_cache_save", C.c_int, [C.c_char_p]),
+    ("pn_tune_cache_load", C.c_int, [C.c_char_p]),
+    ("pn_tune_cache_size", C.c_int, []),
+    ("pn_tune_cache_clear", None, []),
+    ("pn_batch_setup", C.c_int, [C.c_int, C.POINTER(PnProblem), C.c_int, C.c_int, C.c_void_p,
+                                 C.POINTER(C.c_void_p)]),
+    ("pn_batch_layout", C.c_int, [C.c_void_p, C.c_int, C.POINTER(PnLayout)]),
+    ("pn_batch_zchunk", C.c_int, [C.c_void_p, C.c_int]),
+    ("pn_batch_unknowns", C.c_longlong, [C.c_void_p]),
+    ("pn_batch_solve", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double,
+                                 C.POINTER(PnSolveOpts), C.POINTER(PnSolveInfo)]),
+    ("pn_batch_bench_apply", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
+    ("pn_batch_destroy", None, [C.c_void_p]),
+    ("pn_batch_last_error", C.c_char_p, [C.c_void_p]),
 ]
 
 _lib = None

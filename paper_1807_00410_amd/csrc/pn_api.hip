@@ -9,86 +9,19 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 
 #include "../../include/pn.h"
-#include "pn_launch.h"
+#include "pn_internal.h"
 
-namespace pn {  // instantiated in pn_order_N.hip
-extern template hipError_t launch_order<1>(int, bool, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_order<2>(int, bool, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_order<3>(int, bool, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_order<4>(int, bool, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_order<5>(int, bool, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_order<6>(int, bool, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_order<7>(int, bool, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_lds_order<1>(int, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_lds_order<2>(int, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_lds_order<3>(int, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_lds_order<4>(int, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_lds_order<5>(int, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_lds_order<6>(int, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t launch_lds_order<7>(int, bool, const StencilArgs&, hipStream_t);
-extern template hipError_t lds_prepare<1>(size_t);
-extern template hipError_t lds_prepare<2>(size_t);
-extern template hipError_t lds_prepare<3>(size_t);
-extern template hipError_t lds_prepare<4>(size_t);
-extern template hipError_t lds_prepare<5>(size_t);
-extern template hipError_t lds_prepare<6>(size_t);
-extern template hipError_t lds_prepare<7>(size_t);
-}  // namespace pn
 
 using namespace pn;
 
-namespace {
 thread_local std::string g_setup_error;
-}
 
-struct pn_ctx {
-  int order = 0, nc = 0;
-  int nx = 0, ny = 0, nz = 0, bc = 0;
-  double h = 0.0;
-  float g = 0.f, thr = 0.f;
-  hipStream_t stream = nullptr;   // caller's stream
-  hipStream_t sstream = nullptr;  // solve stream (graph capture needs a non-null stream)
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  long n = 0;
-  int off[kMaxCoeff] = {};
-  int ext[kMaxCoeff][3] = {};
-  int cls[kMaxCoeff][3] = {};
-  float2* med = nullptr;    // padded cells (sigma_t thresholded, albedo)
-  float2* med32 = nullptr;  // padded cells (sigma_a, sigma_s) FP32
-  // padded lattice geometry (see StencilArgs)
-  int PX = 0, PY = 0, plane = 0, CX = 0, cplane = 0;
-  long long cs = 0, nv = 0;  // coefficient stride, padded vector length
-  // FP32 Krylov workspace on the padded lattice (r ping-pong, s, p, q, d, rhs)
-  float* r32[2] = {nullptr, nullptr};
-  float *s32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr, *b32 = nullptr;
-  double* x64 = nullptr;    // FP64 iterate (padded)
-  // FP64 Krylov workspace, allocated on first use
-  double* r64[2] = {nullptr, nullptr};
-  double *s64 = nullptr, *p64 = nullptr, *q64 = nullptr, *d64 = nullptr;
-  DevState* st = nullptr;
-  DevState* st_host = nullptr;
-  double* partials = nullptr;
-  int* flag = nullptr;
-  int* flag_host = nullptr;
-  // launch geometry
-  int Ex = 0, Ey = 0, Ez = 0;
-  int zchunk = 0, nzc = 0, ncb = 0, nblocks = 0;
-  int max_blocks = 0;
-  // captured inner iterations
-  hipGraphExec_t gexec32 = nullptr, gexec64 = nullptr;
-  int giters32 = 0, giters64 = 0;
-  // LDS-tiled FP32 stencil (vacuum boundary): tile shape and z chunking
-  int lds_ok = 0;   // the tiled kernel fits this context
-  int use_lds = 0;  // applies and the CG variant use it (opt-in, pn_set_tiles)
-  int TX = 0, TY = 0, ntx = 0, nty = 0, lzchunk = 0, lnzc = 0, lnblocks = 0;
-  size_t lds_bytes = 0, lds_max = 0;
-  hipGraphExec_t gexec_cg = nullptr;  // captured CG-on-normal-equations iterations
-  int giters_cg = 0;
-  std::string err;
-};
 
 static constexpr size_t kLdsMax = 160 * 1024;
 
@@ -136,7 +69,6 @@ static void choose_tiles(pn_ctx* c) {
   c->lds_ok = (bx > 0) && set_tiles(c, bx, by, 0);
 }
 
-static StencilArgs base_args(const pn_ctx* c);
 
 // LDS-tiled FP32 apply: mode M_APPLY (norm optional) or M_SUPD.
 static hipError_t launch_lds(const pn_ctx* c, int mode, bool norm, StencilArgs a, hipStream_t s) {
@@ -168,26 +100,20 @@ static hipError_t lds_prepare_order(int order, size_t bytes) {
 }
 
 // ------------------------------------------------------------ utilities --
-#define PN_HIP(call)                                                              \
-  do {                                                                            \
-    hipError_t e_ = (call);                                                       \
-    if (e_ != hipSuccess) return fail(c, PN_ERR_HIP, std::string(#call) + ": " +  \
-                                       hipGetErrorString(e_));                    \
-  } while (0)
 
-static pn_status fail(pn_ctx* c, pn_status s, const std::string& msg) {
+pn_status fail(pn_ctx* c, pn_status s, const std::string& msg) {
   if (c) c->err = msg; else g_setup_error = msg;
   return s;
 }
 
-static int grid_for(long n) {
+int grid_for(long n) {
   long b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
   if (b < 1) b = 1;
   return (int)b;
 }
 
-static void set_geometry(pn_ctx* c, int zchunk) {
+void set_geometry(pn_ctx* c, int zchunk) {
   const int per = c->bc == PN_BC_PERIODIC;
   c->Ex = c->nx + (per ? 0 : 1);
   c->Ey = c->ny + (per ? 0 : 1);
@@ -212,7 +138,7 @@ static void set_geometry(pn_ctx* c, int zchunk) {
   c->nblocks = c->ncb * c->nzc;
 }
 
-static StencilArgs base_args(const pn_ctx* c) {
+StencilArgs base_args(const pn_ctx* c) {
   StencilArgs a;
   std::memset(&a, 0, sizeof(a));
   a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
@@ -230,54 +156,8 @@ static StencilArgs base_args(const pn_ctx* c) {
   return a;
 }
 
-static PackArgs pack_args(const pn_ctx* c) {
-  PackArgs p;
-  std::memset(&p, 0, sizeof(p));
-  p.nc = c->nc; p.PX = c->PX; p.PY = c->PY; p.plane = c->plane; p.cs = c->cs;
-  for (int k = 0; k < c->nc; ++k) {
-    p.off[k] = c->off[k];
-    p.ex[k] = c->ext[k][0]; p.ey[k] = c->ext[k][1]; p.ez[k] = c->ext[k][2];
-  }
-  return p;
-}
 
-// DIR 0: padded <- packed; 1: packed <- padded; 2: packed += padded
-template <typename TS, typename TD, int DIR>
-static hipError_t launch_pack(const pn_ctx* c, const TS* src, TD* dst, hipStream_t s) {
-  long long maxsz = 0;
-  for (int k = 0; k < c->nc; ++k) {
-    long long sz = (long long)c->ext[k][0] * c->ext[k][1] * c->ext[k][2];
-    if (sz > maxsz) maxsz = sz;
-  }
-  long long bx = (maxsz + kBlock - 1) / kBlock;
-  if (bx > 1024) bx = 1024;
-  hipLaunchKernelGGL((k_pack<TS, TD, DIR>), dim3((unsigned)bx, c->nc), dim3(kBlock), 0, s, src, dst, pack_args(c));
-  return hipGetLastError();
-}
 
-// Dispatch on order (one translation unit per order) and boundary type; APPLY
-// launches reduce ||y||^2 only when a.partials is set (the Krylov loop), the
-// other modes always do.
-template <typename T, int MODE, typename TO>
-static hipError_t launch_stencil(const pn_ctx* c, const StencilArgs& a, hipStream_t s) {
-  const bool per = c->bc == PN_BC_PERIODIC;
-  const bool norm = !(MODE == M_APPLY && a.partials == nullptr);
-  int kind;
-  if constexpr (sizeof(T) == 4) kind = (MODE == M_APPLY) ? K_F32_APPLY : K_F32_TRANSR;
-  else if constexpr (MODE == M_APPLY) kind = K_F64_APPLY;
-  else if constexpr (MODE == M_TRANSR) kind = K_F64_TRANSR;
-  else kind = (sizeof(TO) == 4) ? K_F64_RESID32 : K_F64_RESID64;
-  switch (c->order) {
-    case 1: return launch_order<1>(kind, per, norm, a, s);
-    case 2: return launch_order<2>(kind, per, norm, a, s);
-    case 3: return launch_order<3>(kind, per, norm, a, s);
-    case 4: return launch_order<4>(kind, per, norm, a, s);
-    case 5: return launch_order<5>(kind, per, norm, a, s);
-    case 6: return launch_order<6>(kind, per, norm, a, s);
-    case 7: return launch_order<7>(kind, per, norm, a, s);
-    default: return hipErrorInvalidValue;
-  }
-}
 
 static void free_all(pn_ctx* c) {
   if (!c) return;
@@ -327,8 +207,138 @@ extern "C" const char* pn_last_error(const pn_ctx* c) {
   return c ? c->err.c_str() : g_setup_error.c_str();
 }
 
-extern "C" pn_status pn_setup(int order, const pn_grid* grid, const pn_medium* med, void* stream,
-                              pn_ctx** out) {
+// ------------------------------------------------------------- autotuner --
+// Launch tuning of the register-window stencil: the number of z planes a
+// block marches (zchunk) trades launch width against the re-read of the
+// window planes at chunk borders.  Candidates are timed on the device and the
+// fastest is kept in a process-wide cache keyed by (order, grid, boundary),
+// which contexts consult at setup and which can be saved to / loaded from a
+// text file.
+namespace {
+struct TuneKey {
+  int order, nx, ny, nz, bc;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(order, nx, ny, nz, bc) < std::tie(o.order, o.nx, o.ny, o.nz, o.bc);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, double>> g_tune;
+TuneKey key_of(const pn_ctx* c) { return TuneKey{c->order, c->nx, c->ny, c->nz, c->bc}; }
+}  // namespace
+
+bool tune_lookup(const pn_ctx* c, int* zchunk, double* ms) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key_of(c));
+  if (it == g_tune.end()) return false;
+  if (zchunk) *zchunk = it->second.first;
+  if (ms) *ms = it->second.second;
+  return true;
+}
+
+void tune_store(const pn_ctx* c, int zchunk, double ms) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key_of(c)] = {zchunk, ms};
+}
+
+int tune_zchunk(pn_ctx* c, const float* x, float* y, int iters, double* best_ms) {
+  static const int cand[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = c->zchunk;
+  double bms = -1.0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return -1;
+  }
+  bool ok = true;
+  for (int z : cand) {
+    if (z > c->Ez && z != cand[0]) break;
+    set_geometry(c, z);
+    if (c->nblocks > c->max_blocks) continue;
+    StencilArgs a = base_args(c);
+    a.x = x; a.y = y;
+    ok = ok && launch_stencil<float, M_APPLY, float>(c, a, c->stream) == hipSuccess;  // warm-up
+    ok = ok && hipEventRecord(e0, c->stream) == hipSuccess;
+    for (int i = 0; i < iters && ok; ++i) ok = launch_stencil<float, M_APPLY, float>(c, a, c->stream) == hipSuccess;
+    ok = ok && hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (!ok) break;
+    const double per = (double)ms / iters;
+    if (bms < 0.0 || per < bms) { bms = per; best = c->zchunk; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  set_geometry(c, best);
+  if (!ok) return -1;
+  if (best_ms) *best_ms = bms;
+  return best;
+}
+
+extern "C" pn_status pn_autotune(pn_ctx* c, int iters, int* zchunk, double* ms) {
+  if (!c) return PN_ERR_ARG;
+  if (iters < 1) return fail(c, PN_ERR_ARG, "iters must be >= 1");
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no workspace");
+  double bms = 0.0;
+  const int z = tune_zchunk(c, c->p32, c->q32, iters, &bms);
+  if (z < 0) return fail(c, PN_ERR_HIP, "autotune: a timing launch failed");
+  tune_store(c, z, bms);
+  if (c->gexec32) { hipGraphExecDestroy(c->gexec32); c->gexec32 = nullptr; c->giters32 = 0; }
+  if (c->gexec64) { hipGraphExecDestroy(c->gexec64); c->gexec64 = nullptr; c->giters64 = 0; }
+  if (zchunk) *zchunk = z;
+  if (ms) *ms = bms;
+  return PN_OK;
+}
+
+extern "C" int pn_tune_cache_size(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int)g_tune.size();
+}
+
+extern "C" void pn_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+extern "C" pn_status pn_tune_cache_save(const char* path) {
+  if (!path) return PN_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return PN_ERR_ARG;
+  std::fprintf(f, "# pn stencil tune cache: order nx ny nz bc zchunk ms\n");
+  for (const auto& kv : g_tune)
+    std::fprintf(f, "%d %d %d %d %d %d %.6f\n", kv.first.order, kv.first.nx, kv.first.ny, kv.first.nz, kv.first.bc,
+                 kv.second.first, kv.second.second);
+  const bool bad = std::ferror(f) != 0;
+  std::fclose(f);
+  return bad ? PN_ERR_ARG : PN_OK;
+}
+
+extern "C" pn_status pn_tune_cache_load(const char* path) {
+  if (!path) return PN_ERR_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return PN_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  char line[256];
+  pn_status st = PN_OK;
+  while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    TuneKey k{};
+    int z = 0;
+    double ms = 0.0;
+    if (std::sscanf(line, "%d %d %d %d %d %d %lf", &k.order, &k.nx, &k.ny, &k.nz, &k.bc, &z, &ms) != 7 ||
+        k.order < 1 || k.order > PN_MAX_ORDER || k.nx < 1 || k.ny < 1 || k.nz < 1 || z < 1 ||
+        (k.bc != PN_BC_VACUUM && k.bc != PN_BC_PERIODIC)) {
+      st = PN_ERR_ARG;
+      break;
+    }
+    g_tune[k] = {z, ms};
+  }
+  std::fclose(f);
+  return st;
+}
+
+pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* stream, bool workspace,
+                    pn_ctx** out) {
   pn_ctx* c = nullptr;
   if (!out) return fail(nullptr, PN_ERR_ARG, "out is NULL");
   *out = nullptr;
@@ -398,16 +408,18 @@ extern "C" pn_status pn_setup(int order, const pn_grid* grid, const pn_medium* m
   const long long pcells = (long long)(c->nx + 2) * (c->ny + 2) * (c->nz + 2);
   SETUP_HIP(hipMalloc(&c->med, sizeof(float2) * pcells));
   SETUP_HIP(hipMalloc(&c->med32, sizeof(float2) * pcells));
-  float** v32[] = {&c->r32[0], &c->r32[1], &c->s32, &c->p32, &c->q32, &c->d32, &c->b32};
-  for (float** v : v32) {
-    SETUP_HIP(hipMalloc(v, sizeof(float) * c->nv));
-    SETUP_HIP(hipMemsetAsync(*v, 0, sizeof(float) * c->nv, c->stream));  // zero halo invariant
+  if (workspace) {
+    float** v32[] = {&c->r32[0], &c->r32[1], &c->s32, &c->p32, &c->q32, &c->d32, &c->b32};
+    for (float** v : v32) {
+      SETUP_HIP(hipMalloc(v, sizeof(float) * c->nv));
+      SETUP_HIP(hipMemsetAsync(*v, 0, sizeof(float) * c->nv, c->stream));  // zero halo invariant
+    }
+    SETUP_HIP(hipMalloc(&c->x64, sizeof(double) * c->nv));
+    SETUP_HIP(hipMemsetAsync(c->x64, 0, sizeof(double) * c->nv, c->stream));
+    SETUP_HIP(hipMalloc(&c->st, sizeof(DevState)));
+    SETUP_HIP(hipHostMalloc(&c->st_host, sizeof(DevState), hipHostMallocDefault));
+    SETUP_HIP(hipMalloc(&c->partials, sizeof(double) * 2 * c->max_blocks));
   }
-  SETUP_HIP(hipMalloc(&c->x64, sizeof(double) * c->nv));
-  SETUP_HIP(hipMemsetAsync(c->x64, 0, sizeof(double) * c->nv, c->stream));
-  SETUP_HIP(hipMalloc(&c->st, sizeof(DevState)));
-  SETUP_HIP(hipHostMalloc(&c->st_host, sizeof(DevState), hipHostMallocDefault));
-  SETUP_HIP(hipMalloc(&c->partials, sizeof(double) * 2 * c->max_blocks));
   SETUP_HIP(hipMalloc(&c->flag, sizeof(int)));
   SETUP_HIP(hipHostMalloc(&c->flag_host, sizeof(int), hipHostMallocDefault));
 
@@ -434,8 +446,23 @@ extern "C" pn_status pn_setup(int order, const pn_grid* grid, const pn_medium* m
   }
   choose_tiles(c);
 #undef SETUP_HIP
+  {
+    int z = 0;
+    if (tune_lookup(c, &z, nullptr)) set_geometry(c, z);
+  }
   *out = c;
   return PN_OK;
+}
+
+extern "C" pn_status pn_setup(int order, const pn_grid* grid, const pn_medium* med, void* stream,
+                              pn_ctx** out) {
+  return setup_ctx(order, grid, med, stream, true, out);
+}
+
+void free_ctx(pn_ctx* c) {
+  if (!c) return;
+  free_all(c);
+  delete c;
 }
 
 extern "C" pn_status pn_set_zchunk(pn_ctx* c, int zchunk) {

@@ -1,0 +1,165 @@
+// Internal declarations shared by the C-ABI translation units (not part of
+// the public interface): the solver context and the host-side helpers that
+// set up its padded geometry, pack vectors and dispatch the stencil kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "../../include/pn.h"
+#include "pn_launch.h"
+
+namespace pn {  // instantiated in pn_order_N.hip
+extern template hipError_t launch_order<1>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<2>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<3>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<4>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<5>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<6>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_order<7>(int, bool, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<1>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<2>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<3>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<4>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<5>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<6>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t launch_lds_order<7>(int, bool, const StencilArgs&, hipStream_t);
+extern template hipError_t lds_prepare<1>(size_t);
+extern template hipError_t lds_prepare<2>(size_t);
+extern template hipError_t lds_prepare<3>(size_t);
+extern template hipError_t lds_prepare<4>(size_t);
+extern template hipError_t lds_prepare<5>(size_t);
+extern template hipError_t lds_prepare<6>(size_t);
+extern template hipError_t lds_prepare<7>(size_t);
+extern template hipError_t launch_batch_order<1>(int, bool, const BatchLaunch&, hipStream_t);
+extern template hipError_t launch_batch_order<2>(int, bool, const BatchLaunch&, hipStream_t);
+extern template hipError_t launch_batch_order<3>(int, bool, const BatchLaunch&, hipStream_t);
+extern template hipError_t launch_batch_order<4>(int, bool, const BatchLaunch&, hipStream_t);
+extern template hipError_t launch_batch_order<5>(int, bool, const BatchLaunch&, hipStream_t);
+extern template hipError_t launch_batch_order<6>(int, bool, const BatchLaunch&, hipStream_t);
+extern template hipError_t launch_batch_order<7>(int, bool, const BatchLaunch&, hipStream_t);
+}  // namespace pn
+
+using namespace pn;
+
+struct pn_ctx {
+  int order = 0, nc = 0;
+  int nx = 0, ny = 0, nz = 0, bc = 0;
+  double h = 0.0;
+  float g = 0.f, thr = 0.f;
+  hipStream_t stream = nullptr;   // caller's stream
+  hipStream_t sstream = nullptr;  // solve stream (graph capture needs a non-null stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  long n = 0;
+  int off[kMaxCoeff] = {};
+  int ext[kMaxCoeff][3] = {};
+  int cls[kMaxCoeff][3] = {};
+  float2* med = nullptr;    // padded cells (sigma_t thresholded, albedo)
+  float2* med32 = nullptr;  // padded cells (sigma_a, sigma_s) FP32
+  // padded lattice geometry (see StencilArgs)
+  int PX = 0, PY = 0, plane = 0, CX = 0, cplane = 0;
+  long long cs = 0, nv = 0;  // coefficient stride, padded vector length
+  // FP32 Krylov workspace on the padded lattice (r ping-pong, s, p, q, d, rhs)
+  float* r32[2] = {nullptr, nullptr};
+  float *s32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr, *b32 = nullptr;
+  double* x64 = nullptr;    // FP64 iterate (padded)
+  // FP64 Krylov workspace, allocated on first use
+  double* r64[2] = {nullptr, nullptr};
+  double *s64 = nullptr, *p64 = nullptr, *q64 = nullptr, *d64 = nullptr;
+  DevState* st = nullptr;
+  DevState* st_host = nullptr;
+  double* partials = nullptr;
+  int* flag = nullptr;
+  int* flag_host = nullptr;
+  // launch geometry
+  int Ex = 0, Ey = 0, Ez = 0;
+  int zchunk = 0, nzc = 0, ncb = 0, nblocks = 0;
+  int max_blocks = 0;
+  // captured inner iterations
+  hipGraphExec_t gexec32 = nullptr, gexec64 = nullptr;
+  int giters32 = 0, giters64 = 0;
+  // LDS-tiled FP32 stencil (vacuum boundary): tile shape and z chunking
+  int lds_ok = 0;   // the tiled kernel fits this context
+  int use_lds = 0;  // applies and the CG variant use it (opt-in, pn_set_tiles)
+  int TX = 0, TY = 0, ntx = 0, nty = 0, lzchunk = 0, lnzc = 0, lnblocks = 0;
+  size_t lds_bytes = 0, lds_max = 0;
+  hipGraphExec_t gexec_cg = nullptr;  // captured CG-on-normal-equations iterations
+  int giters_cg = 0;
+  std::string err;
+};
+
+
+#define PN_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) return fail(c, PN_ERR_HIP, std::string(#call) + ": " +  \
+                                       hipGetErrorString(e_));                    \
+  } while (0)
+
+extern thread_local std::string g_setup_error;
+pn_status fail(pn_ctx* c, pn_status s, const std::string& msg);
+int grid_for(long n);
+void set_geometry(pn_ctx* c, int zchunk);
+StencilArgs base_args(const pn_ctx* c);
+// Context with geometry and medium; the Krylov workspace only if `workspace`.
+pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* stream, bool workspace,
+                    pn_ctx** out);
+// Mean milliseconds of one FP32 apply (register kernel, no reduction) for
+// each zchunk candidate on padded vectors x -> y; sets the fastest and returns it.
+int tune_zchunk(pn_ctx* c, const float* x, float* y, int iters, double* best_ms);
+bool tune_lookup(const pn_ctx* c, int* zchunk, double* ms);
+void tune_store(const pn_ctx* c, int zchunk, double ms);
+void free_ctx(pn_ctx* c);
+
+inline PackArgs pack_args(const pn_ctx* c) {
+  PackArgs p;
+  std::memset(&p, 0, sizeof(p));
+  p.nc = c->nc; p.PX = c->PX; p.PY = c->PY; p.plane = c->plane; p.cs = c->cs;
+  for (int k = 0; k < c->nc; ++k) {
+    p.off[k] = c->off[k];
+    p.ex[k] = c->ext[k][0]; p.ey[k] = c->ext[k][1]; p.ez[k] = c->ext[k][2];
+  }
+  return p;
+}
+
+
+// DIR 0: padded <- packed; 1: packed <- padded; 2: packed += padded
+template <typename TS, typename TD, int DIR>
+inline hipError_t launch_pack(const pn_ctx* c, const TS* src, TD* dst, hipStream_t s) {
+  long long maxsz = 0;
+  for (int k = 0; k < c->nc; ++k) {
+    long long sz = (long long)c->ext[k][0] * c->ext[k][1] * c->ext[k][2];
+    if (sz > maxsz) maxsz = sz;
+  }
+  long long bx = (maxsz + kBlock - 1) / kBlock;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL((k_pack<TS, TD, DIR>), dim3((unsigned)bx, c->nc), dim3(kBlock), 0, s, src, dst, pack_args(c));
+  return hipGetLastError();
+}
+
+
+// Dispatch on order (one translation unit per order) and boundary type; APPLY
+// launches reduce ||y||^2 only when a.partials is set (the Krylov loop), the
+// other modes always do.
+template <typename T, int MODE, typename TO>
+inline hipError_t launch_stencil(const pn_ctx* c, const StencilArgs& a, hipStream_t s) {
+  const bool per = c->bc == PN_BC_PERIODIC;
+  const bool norm = !(MODE == M_APPLY && a.partials == nullptr);
+  int kind;
+  if constexpr (sizeof(T) == 4) kind = (MODE == M_APPLY) ? K_F32_APPLY : K_F32_TRANSR;
+  else if constexpr (MODE == M_APPLY) kind = K_F64_APPLY;
+  else if constexpr (MODE == M_TRANSR) kind = K_F64_TRANSR;
+  else kind = (sizeof(TO) == 4) ? K_F64_RESID32 : K_F64_RESID64;
+  switch (c->order) {
+    case 1: return launch_order<1>(kind, per, norm, a, s);
+    case 2: return launch_order<2>(kind, per, norm, a, s);
+    case 3: return launch_order<3>(kind, per, norm, a, s);
+    case 4: return launch_order<4>(kind, per, norm, a, s);
+    case 5: return launch_order<5>(kind, per, norm, a, s);
+    case 6: return launch_order<6>(kind, per, norm, a, s);
+    case 7: return launch_order<7>(kind, per, norm, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+

@@ -47,12 +47,14 @@ struct DevState {
   double rtrue2;  // ||Q - A x||^2 from the FP64 residual kernel
   double bb2;     // ||Q||^2
   double nonfinite;
+  double itol2;   // batch: squared relative tolerance of the next inner solve
   int iters;      // Krylov iterations so far (all inner solves)
   int max_iters;
   int stop;       // set when the iteration must end after this step's update
   int done;       // set one step later: every kernel returns at once
   int breakdown;
-  int pad[3];
+  int frozen;     // batch: the system is finished; every kernel skips it
+  int pad[2];
 };
 
 // M_SUPD: s <- s - alpha * op(x) (the normal-equation residual update of CG
@@ -159,14 +161,9 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 //   M_TRANSR r' = r - alpha q, y = A^T r'      [writes r' to y2; ||y||^2, ||r'||^2]
 //   M_RESID  y = Q - A x                       [||y||^2, ||Q||^2]
 template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
-__global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil(const StencilArgs a) {
+__device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) {
   using TB = Table<N>;
   constexpr int NC = TB::NC;
-  constexpr int NCPL = TB::NCPL;
-  // In the Krylov loop the A p launch also ends once the stop flag is up.
-  if (a.st != nullptr && (a.st->done || (MODE == M_APPLY && a.st->stop))) return;
-
-  const int L = xcd_remap(blockIdx.x, a.nblocks);
   const int cb = L % a.ncb, zc = L / a.ncb;
   const int col = cb * kBlock + threadIdx.x;
   const bool act = col < a.Ex * a.Ey;
@@ -375,6 +372,53 @@ __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil(const Stenci
   }
 }
 
+template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
+__global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil(const StencilArgs a) {
+  // In the Krylov loop the A p launch also ends once the stop flag is up.
+  if (a.st != nullptr && (a.st->done || (MODE == M_APPLY && a.st->stop))) return;
+  stencil_body<N, T, MODE, TO, PER, NORM>(a, xcd_remap(blockIdx.x, a.nblocks));
+}
+
+// ---------------------------------------------------------------- batch --
+// Many systems (problem x right-hand side) in one launch.  Each block takes a
+// work item (system, tile) from a list ordered problem-major, then tile, then
+// right-hand side, so the blocks of one tile for the different right-hand
+// sides of a problem run next to each other on one XCD and share the cell
+// parameters through its L2.  A system's vectors are addressed by role
+// through its vector table.
+enum BatchVec { BV_R0 = 0, BV_R1, BV_S, BV_P, BV_Q, BV_D, BV_B, BV_X64, BV_COUNT };
+
+struct SysArgs {
+  StencilArgs a;        // geometry and medium of the problem; st, partials of the system
+  void* vec[BV_COUNT];  // padded vectors of the system
+  long long nv;         // padded vector length
+  double itol2;         // squared relative inner tolerance of the current inner solve
+};
+
+struct BatchLaunch {
+  const SysArgs* sys;
+  const int2* work;     // (system, tile) per block
+  int nwork;
+  int ix, ix2, iy, iy2; // vector roles (-1: unused)
+  double tsign;
+  int gate;             // 1: skip systems whose inner solve stopped (Krylov loop)
+};
+
+template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
+__global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil_batch(const BatchLaunch bl) {
+  const int2 w = bl.work[xcd_remap(blockIdx.x, bl.nwork)];
+  const SysArgs* __restrict__ s = bl.sys + w.x;
+  DevState* st = s->a.st;
+  if (st->frozen || (bl.gate && (st->done || (MODE == M_APPLY && st->stop)))) return;
+  StencilArgs a = s->a;
+  a.x = s->vec[bl.ix];
+  a.x2 = bl.ix2 >= 0 ? s->vec[bl.ix2] : nullptr;
+  a.y = s->vec[bl.iy];
+  a.y2 = bl.iy2 >= 0 ? s->vec[bl.iy2] : nullptr;
+  a.tsign = bl.tsign;
+  stencil_body<N, T, MODE, TO, PER, NORM>(a, w.y);
+}
+
 // ------------------------------------------------------------- finalize --
 // Sum of partials[2*i + j] over i < n in a fixed order (one block).
 __device__ __forceinline__ void grid_sum2(const double* __restrict__ p, int n, double& s0, double& s1) {
@@ -398,7 +442,7 @@ __device__ __forceinline__ void grid_sum2(const double* __restrict__ p, int n, d
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
 
 // After q = A p:  alpha = gamma / ||q||^2.
-static __global__ void __launch_bounds__(kBlock) k_fin_alpha(DevState* st, const double* partials, int n) {
+__device__ __forceinline__ void fin_alpha(DevState* st, const double* partials, int n) {
   if (st->done) return;
   if (st->stop) {
     if (threadIdx.x == 0) st->done = 1;
@@ -420,7 +464,7 @@ static __global__ void __launch_bounds__(kBlock) k_fin_alpha(DevState* st, const
 }
 
 // After s = A^T r':  beta = ||s||^2 / gamma, convergence test on ||r'||^2.
-static __global__ void __launch_bounds__(kBlock) k_fin_beta(DevState* st, const double* partials, int n) {
+__device__ __forceinline__ void fin_beta(DevState* st, const double* partials, int n) {
   if (st->done) return;
   double ss, rr;
   grid_sum2(partials, n, ss, rr);
@@ -436,7 +480,7 @@ static __global__ void __launch_bounds__(kBlock) k_fin_beta(DevState* st, const 
 }
 
 // After s = A^T r0, p = s:  start of an inner solve.
-static __global__ void __launch_bounds__(kBlock) k_fin_init(DevState* st, const double* partials, int n, double inner_tol2) {
+__device__ __forceinline__ void fin_init(DevState* st, const double* partials, int n, double inner_tol2) {
   double ss, unused;
   grid_sum2(partials, n, ss, unused);
   if (threadIdx.x == 0) {
@@ -456,7 +500,7 @@ static __global__ void __launch_bounds__(kBlock) k_fin_init(DevState* st, const 
 // p <- s + beta p).  The residual norm follows ||r'||^2 = ||r||^2 - alpha gamma
 // (r' = r - alpha q and <r, q> = <s, p> = gamma), so r itself is never formed.
 // After q = A p:
-static __global__ void __launch_bounds__(kBlock) k_fin_alpha_cg(DevState* st, const double* partials, int n) {
+__device__ __forceinline__ void fin_alpha_cg(DevState* st, const double* partials, int n) {
   if (st->done) return;
   if (st->stop) {
     if (threadIdx.x == 0) st->done = 1;
@@ -482,7 +526,7 @@ static __global__ void __launch_bounds__(kBlock) k_fin_alpha_cg(DevState* st, co
 }
 
 // After s <- s - alpha A^T q (partials hold ||s||^2):
-static __global__ void __launch_bounds__(kBlock) k_fin_beta_cg(DevState* st, const double* partials, int n) {
+__device__ __forceinline__ void fin_beta_cg(DevState* st, const double* partials, int n) {
   if (st->done || st->stop) return;
   double ss, unused;
   grid_sum2(partials, n, ss, unused);
@@ -496,7 +540,7 @@ static __global__ void __launch_bounds__(kBlock) k_fin_beta_cg(DevState* st, con
 }
 
 // After r = Q - A x (FP64):  true residual and ||Q||^2.
-static __global__ void __launch_bounds__(kBlock) k_fin_resid(DevState* st, const double* partials, int n) {
+__device__ __forceinline__ void fin_resid(DevState* st, const double* partials, int n) {
   double rr, bb;
   grid_sum2(partials, n, rr, bb);
   if (threadIdx.x == 0) {
@@ -505,6 +549,13 @@ static __global__ void __launch_bounds__(kBlock) k_fin_resid(DevState* st, const
     st->rr = rr;
   }
 }
+
+static __global__ void __launch_bounds__(kBlock) k_fin_alpha(DevState* st, const double* partials, int n) { fin_alpha(st, partials, n); }
+static __global__ void __launch_bounds__(kBlock) k_fin_beta(DevState* st, const double* partials, int n) { fin_beta(st, partials, n); }
+static __global__ void __launch_bounds__(kBlock) k_fin_init(DevState* st, const double* partials, int n, double inner_tol2) { fin_init(st, partials, n, inner_tol2); }
+static __global__ void __launch_bounds__(kBlock) k_fin_alpha_cg(DevState* st, const double* partials, int n) { fin_alpha_cg(st, partials, n); }
+static __global__ void __launch_bounds__(kBlock) k_fin_beta_cg(DevState* st, const double* partials, int n) { fin_beta_cg(st, partials, n); }
+static __global__ void __launch_bounds__(kBlock) k_fin_resid(DevState* st, const double* partials, int n) { fin_resid(st, partials, n); }
 
 // ---------------------------------------------------------------- vector --
 // x += alpha p;  p = s + beta p
@@ -619,6 +670,89 @@ static __global__ void __launch_bounds__(kBlock) k_check_finite(const float* __r
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
     if (!isfinite(v[i])) b = 1;
   if (b) atomicOr(bad, 1);
+}
+
+
+// ------------------------------------------------------- batch (scalars) --
+// One block per system; a finished (frozen) system is skipped.
+enum BatchFin { BF_ALPHA = 0, BF_BETA = 1, BF_INIT = 2, BF_RESID = 3 };
+
+template <int WHICH>
+__global__ void __launch_bounds__(kBlock) k_fin_batch(const SysArgs* __restrict__ sys) {
+  const SysArgs* s = sys + blockIdx.x;
+  DevState* st = s->a.st;
+  if (st->frozen) return;
+  const double* p = s->a.partials;
+  const int n = s->a.nblocks;
+  if constexpr (WHICH == BF_ALPHA) fin_alpha(st, p, n);
+  else if constexpr (WHICH == BF_BETA) fin_beta(st, p, n);
+  else if constexpr (WHICH == BF_INIT) fin_init(st, p, n, st->itol2);
+  else fin_resid(st, p, n);
+}
+
+// Number of systems whose inner solve is still running (one block).
+static __global__ void __launch_bounds__(kBlock) k_batch_active(const SysArgs* __restrict__ sys, int nsys,
+                                                               int* __restrict__ out) {
+  __shared__ int cnt[kBlock];
+  int c = 0;
+  for (int i = threadIdx.x; i < nsys; i += kBlock) {
+    const DevState* st = sys[i].a.st;
+    c += (!st->frozen && !st->done) ? 1 : 0;
+  }
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = cnt[0];
+}
+
+// ------------------------------------------------------- batch (vectors) --
+// Work item (system, chunk): elements [chunk*kChunk, min((chunk+1)*kChunk, nv))
+// of the system's padded vectors.  nv is a multiple of 64, so a chunk is a
+// whole number of float4.
+constexpr int kChunk = 8192;
+enum BatchOp { BO_UPDATE_XP = 0, BO_ZERO_D = 1, BO_COPY_SP = 2, BO_AXPY64 = 3 };
+
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_vec_batch(const SysArgs* __restrict__ sys, const int2* __restrict__ work,
+                                                      int nwork) {
+  const int2 w = work[xcd_remap(blockIdx.x, nwork)];
+  const SysArgs* s = sys + w.x;
+  const DevState* st = s->a.st;
+  if (st->frozen) return;
+  if (OP == BO_UPDATE_XP && st->done) return;
+  const long long i0 = (long long)w.y * kChunk;
+  const long long i1 = min(i0 + (long long)kChunk, s->nv);
+  float* d = static_cast<float*>(s->vec[BV_D]);
+  float* p = static_cast<float*>(s->vec[BV_P]);
+  const float* sv = static_cast<const float*>(s->vec[BV_S]);
+  if constexpr (OP == BO_AXPY64) {
+    double* x = static_cast<double*>(s->vec[BV_X64]);
+    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) x[i] += double(d[i]);
+    return;
+  }
+  const float al = float(st->alpha), be = float(st->beta);
+  float4* d4 = reinterpret_cast<float4*>(d);
+  float4* p4 = reinterpret_cast<float4*>(p);
+  const float4* s4 = reinterpret_cast<const float4*>(sv);
+  for (long long i = (i0 >> 2) + threadIdx.x; i < (i1 >> 2); i += kBlock) {
+    if constexpr (OP == BO_UPDATE_XP) {
+      float4 pv = p4[i], xv = d4[i];
+      const float4 q = s4[i];
+      xv.x = __fmaf_rn(al, pv.x, xv.x); xv.y = __fmaf_rn(al, pv.y, xv.y);
+      xv.z = __fmaf_rn(al, pv.z, xv.z); xv.w = __fmaf_rn(al, pv.w, xv.w);
+      pv.x = __fmaf_rn(be, pv.x, q.x); pv.y = __fmaf_rn(be, pv.y, q.y);
+      pv.z = __fmaf_rn(be, pv.z, q.z); pv.w = __fmaf_rn(be, pv.w, q.w);
+      d4[i] = xv;
+      p4[i] = pv;
+    } else if constexpr (OP == BO_ZERO_D) {
+      d4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      p4[i] = s4[i];
+    }
+  }
 }
 
 }  // namespace pn

@@ -43,4 +43,24 @@ hipError_t launch_order(int kind, bool per, bool norm, const StencilArgs& a, hip
   }
 }
 
+// Batched launch over the systems of one order (BatchLaunch.work); the
+// Krylov kinds always reduce.
+template <int N, typename T, int MODE, typename TO>
+hipError_t launch_batch_flavour(bool per, const BatchLaunch& bl, hipStream_t s) {
+  dim3 grid(bl.nwork), block(kBlock);
+  if (per) hipLaunchKernelGGL((k_stencil_batch<N, T, MODE, TO, true, true>), grid, block, 0, s, bl);
+  else hipLaunchKernelGGL((k_stencil_batch<N, T, MODE, TO, false, true>), grid, block, 0, s, bl);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_batch_order(int kind, bool per, const BatchLaunch& bl, hipStream_t s) {
+  switch (kind) {
+    case K_F32_APPLY: return launch_batch_flavour<N, float, M_APPLY, float>(per, bl, s);
+    case K_F32_TRANSR: return launch_batch_flavour<N, float, M_TRANSR, float>(per, bl, s);
+    case K_F64_RESID32: return launch_batch_flavour<N, double, M_RESID, float>(per, bl, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace pn

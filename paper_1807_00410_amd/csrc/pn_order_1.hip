@@ -5,4 +5,5 @@ namespace pn {
 template hipError_t launch_order<1>(int, bool, bool, const StencilArgs&, hipStream_t);
 template hipError_t launch_lds_order<1>(int, bool, const StencilArgs&, hipStream_t);
 template hipError_t lds_prepare<1>(size_t);
+template hipError_t launch_batch_order<1>(int, bool, const BatchLaunch&, hipStream_t);
 }  // namespace pn

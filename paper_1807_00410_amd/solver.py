@@ -112,6 +112,13 @@ class Solver:
         self._check(self.lib.pn_bench_apply(self.ctx, int(iters), int(transpose), C.byref(ms)))
         return ms.value
 
+    def autotune(self, iters=10):
+        """Times the candidate launch z-chunks, keeps the fastest (also in the
+        process-wide tune cache).  Returns (zchunk, ms per apply)."""
+        z, ms = C.c_int(), C.c_double()
+        self._check(self.lib.pn_autotune(self.ctx, int(iters), C.byref(z), C.byref(ms)))
+        return z.value, ms.value
+
     def set_zchunk(self, z):
         self._check(self.lib.pn_set_zchunk(self.ctx, int(z)))
 
@@ -131,21 +138,11 @@ class Solver:
         """Solves A x = rhs.  Returns (x, info dict)."""
         if x is None:
             x = torch.zeros(self.n, dtype=torch.float64, device=rhs.device)
-        opts = L.PnSolveOpts()
-        self.lib.pn_default_opts(C.byref(opts))
-        opts.precision = L.PN_FP64 if precision == "fp64" else L.PN_FP32_IR
-        opts.max_iter = int(max_iter)
-        opts.max_refine = int(max_refine)
-        opts.inner_tol = float(inner_tol)
-        opts.use_guess = int(bool(use_guess))
-        opts.graph_iters = int(graph_iters)
-        opts.variant = {"auto": 0, "cgls": 1, "cg": 2}[variant]
+        opts = _opts(self.lib, precision, max_iter, max_refine, inner_tol, use_guess, graph_iters, variant)
         info = L.PnSolveInfo()
         rc = self.lib.pn_solve(self.ctx, _ptr(rhs, torch.float32), _ptr(x, torch.float64), float(tol),
                                C.byref(opts), C.byref(info))
-        d = dict(status=rc, outer_iters=info.outer_iters, inner_iters=info.inner_iters,
-                 rel_residual=info.rel_residual, bnorm=info.bnorm, seconds=info.seconds,
-                 history=[info.history[i] for i in range(info.nhistory)])
+        d = _info(rc, info)
         if rc != L.PN_OK and raise_on_fail:
             raise PnError(rc, self.lib.pn_last_error(self.ctx).decode())
         return x, d
@@ -157,6 +154,132 @@ class Solver:
         rhs = torch.zeros(self.n, dtype=torch.float32, device=q00.device)
         rhs[self.layout.offset[0]:self.layout.offset[1]] = q00.reshape(-1).to(torch.float32)
         return rhs
+
+
+def _opts(lib, precision, max_iter, max_refine, inner_tol, use_guess, graph_iters, variant):
+    opts = L.PnSolveOpts()
+    lib.pn_default_opts(C.byref(opts))
+    opts.precision = L.PN_FP64 if precision == "fp64" else L.PN_FP32_IR
+    opts.max_iter = int(max_iter)
+    opts.max_refine = int(max_refine)
+    opts.inner_tol = float(inner_tol)
+    opts.use_guess = int(bool(use_guess))
+    opts.graph_iters = int(graph_iters)
+    opts.variant = {"auto": 0, "cgls": 1, "cg": 2}[variant]
+    return opts
+
+
+def _info(rc, info):
+    return dict(status=rc, outer_iters=info.outer_iters, inner_iters=info.inner_iters,
+                rel_residual=info.rel_residual, bnorm=info.bnorm, seconds=info.seconds,
+                history=[info.history[i] for i in range(info.nhistory)])
+
+
+class Batch:
+    """Many media (problems), each with `nrhs` right-hand sides, solved
+    together: pn_batch_setup ... pn_batch_destroy.  `problems` is a list of
+    (order, dims, sigma_t, albedo, g, sigma_t_min, bc) with device FP32 cell
+    arrays."""
+
+    def __init__(self, problems, nrhs, tune=False, h=0.0, stream=None):
+        self.lib = L.load()
+        n = len(problems)
+        arr = (L.PnProblem * n)()
+        keep = []
+        for i, (order, dims, st, al, g, stmin, bc) in enumerate(problems):
+            st = st.contiguous()
+            al = al.contiguous()
+            keep += [st, al]
+            arr[i].order = int(order)
+            arr[i].grid = L.PnGrid(int(dims[0]), int(dims[1]), int(dims[2]), float(h), int(bc))
+            arr[i].medium = L.PnMedium(_ptr(st, torch.float32), _ptr(al, torch.float32), float(g), float(stmin))
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        b = C.c_void_p()
+        rc = self.lib.pn_batch_setup(n, arr, int(nrhs), int(bool(tune)), C.c_void_p(s.cuda_stream), C.byref(b))
+        if rc != L.PN_OK:
+            raise PnError(rc, self.lib.pn_batch_last_error(None).decode())
+        self.b = b
+        self.nprob = n
+        self.nrhs = int(nrhs)
+        self.layouts = []
+        for i in range(n):
+            raw = L.PnLayout()
+            self._check(self.lib.pn_batch_layout(self.b, i, C.byref(raw)))
+            self.layouts.append(Layout(raw))
+
+    def _check(self, rc):
+        if rc != L.PN_OK:
+            raise PnError(rc, self.lib.pn_batch_last_error(self.b).decode())
+
+    @property
+    def unknowns(self):
+        return self.lib.pn_batch_unknowns(self.b)
+
+    def zchunk(self, prob):
+        return self.lib.pn_batch_zchunk(self.b, int(prob))
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.pn_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def bench_apply(self, iters=10, transpose=False):
+        ms = C.c_double()
+        self._check(self.lib.pn_batch_bench_apply(self.b, int(iters), int(transpose), C.byref(ms)))
+        return ms.value
+
+    def solve(self, rhs, x=None, tol=1e-8, max_iter=200000, max_refine=40, inner_tol=1e-3, use_guess=False,
+              graph_iters=32, raise_on_fail=True):
+        """rhs: list over systems (problem-major, nrhs per problem) of device
+        FP32 vectors in the problem's packed layout.  Returns (x list, info list)."""
+        ns = self.nprob * self.nrhs
+        if len(rhs) != ns:
+            raise ValueError("expected %d right-hand sides" % ns)
+        if x is None:
+            x = [torch.zeros(self.layouts[i // self.nrhs].n, dtype=torch.float64, device=rhs[i].device)
+                 for i in range(ns)]
+        rp = (C.c_void_p * ns)(*[_ptr(r, torch.float32).value for r in rhs])
+        xp = (C.c_void_p * ns)(*[_ptr(v, torch.float64).value for v in x])
+        opts = _opts(self.lib, "fp32_ir", max_iter, max_refine, inner_tol, use_guess, graph_iters, "auto")
+        info = (L.PnSolveInfo * ns)()
+        rc = self.lib.pn_batch_solve(self.b, rp, xp, float(tol), C.byref(opts), info)
+        infos = [_info(info[i].status, info[i]) for i in range(ns)]
+        if rc != L.PN_OK and raise_on_fail:
+            raise PnError(rc, self.lib.pn_batch_last_error(self.b).decode())
+        return x, infos
+
+
+def tune_cache_save(path):
+    rc = L.load().pn_tune_cache_save(str(path).encode())
+    if rc != L.PN_OK:
+        raise PnError(rc, "cannot write %s" % path)
+
+
+def tune_cache_load(path):
+    rc = L.load().pn_tune_cache_load(str(path).encode())
+    if rc != L.PN_OK:
+        raise PnError(rc, "cannot read %s" % path)
+
+
+def tune_cache_size():
+    return L.load().pn_tune_cache_size()
+
+
+def tune_cache_clear():
+    L.load().pn_tune_cache_clear()
 
 
 def coupling_table(order):

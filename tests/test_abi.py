@@ -73,3 +73,38 @@ def test_setup_rejects_bad_arguments_on_host(lib):
 def test_status_strings(lib):
     assert lib.pn_status_string(0) == b"ok"
     assert lib.pn_status_string(5) == b"not converged"
+
+
+def test_batch_setup_rejects_bad_arguments_on_host(lib):
+    from paper_1807_00410_amd import _lib as L
+    b = C.c_void_p()
+    probs = (L.PnProblem * 1)()
+    assert lib.pn_batch_setup(0, probs, 1, 0, None, C.byref(b)) == L.PN_ERR_ARG
+    assert lib.pn_batch_setup(1, probs, 0, 0, None, C.byref(b)) == L.PN_ERR_ARG
+    assert lib.pn_batch_setup(1, None, 1, 0, None, C.byref(b)) == L.PN_ERR_ARG
+    assert lib.pn_batch_setup(1, probs, 1, 0, None, None) == L.PN_ERR_ARG
+    assert lib.pn_batch_last_error(None)
+    assert lib.pn_batch_solve(None, None, None, 1e-8, None, None) == L.PN_ERR_ARG
+    assert lib.pn_batch_unknowns(None) == -1
+    assert lib.pn_batch_zchunk(None, 0) == -1
+    lib.pn_batch_destroy(None)
+
+
+def test_tune_cache_file_roundtrip_on_host(lib, tmp_path):
+    from paper_1807_00410_amd import _lib as L
+    lib.pn_tune_cache_clear()
+    src = tmp_path / "in.txt"
+    src.write_text("# comment\n5 128 128 128 0 5 0.2\n3 64 64 64 1 8 0.01\n")
+    assert lib.pn_tune_cache_load(str(src).encode()) == L.PN_OK
+    assert lib.pn_tune_cache_size() == 2
+    out = tmp_path / "out.txt"
+    assert lib.pn_tune_cache_save(str(out).encode()) == L.PN_OK
+    rows = sorted(l.split()[:6] for l in out.read_text().splitlines() if not l.startswith("#"))
+    assert rows == [["3", "64", "64", "64", "1", "8"], ["5", "128", "128", "128", "0", "5"]]
+    bad = tmp_path / "bad.txt"
+    bad.write_text("5 128 128 0 5 0.2\n")
+    assert lib.pn_tune_cache_load(str(bad).encode()) == L.PN_ERR_ARG
+    assert lib.pn_tune_cache_load(str(tmp_path / "missing.txt").encode()) == L.PN_ERR_ARG
+    assert lib.pn_autotune(None, 3, None, None) == L.PN_ERR_ARG
+    lib.pn_tune_cache_clear()
+    assert lib.pn_tune_cache_size() == 0
