@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--apply-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the pure FP64 Krylov comparison solve")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned + mixed-precision solve")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1807_00410_amd", "weights", "unet_p3.bin"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)"
@@ -152,6 +154,35 @@ def main():
         print("[bench] fp64 CGLS: %.3fs iters %d" % (i64["seconds"], i64["inner_iters"]), file=sys.stderr,
               flush=True)
 
+    learned = None
+    if not args.no_learned and os.path.exists(args.weights):
+        from paper_1807_00410_amd.net import Net
+        net = Net(seed=0)
+        net.load(args.weights)
+        s.attach_net(net)
+        for mode in ("guess", "guess+correct"):
+            s.solve(rhs, x=x, tol=args.tol, inner_tol=args.inner_tol, learned=mode)  # warm-up
+        res = {}
+        for mode in ("guess", "guess+correct"):
+            lt, li = [], None
+            for i in range(args.steps):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, li = s.solve(rhs, x=x, tol=args.tol, inner_tol=args.inner_tol, learned=mode)
+                torch.cuda.synchronize()
+                lt.append(time.perf_counter() - t1)
+            res[mode] = {"seconds": sum(lt) / len(lt), "iters": li["inner_iters"], "outer_iters": li["outer_iters"],
+                         "learned_steps": li["learned_steps"], "guess_residual_ratio": li["learned_ratio"],
+                         "rel_residual": li["rel_residual"], "speedup_vs_plain": sec / (sum(lt) / len(lt))}
+            print("[bench] learned %s: %.3fs iters %d outer %d (guess ratio %.3f)" % (
+                mode, res[mode]["seconds"], li["inner_iters"], li["outer_iters"], li["learned_ratio"]),
+                file=sys.stderr, flush=True)
+        learned = {"weights": os.path.relpath(args.weights, ROOT),
+                   "network": "4-level 3D conv U-Net, 32 channels, BF16 MFMA, trained on solver-generated "
+                              "P3 64^3 fBm samples (P3 channels; l = 4, 5 start at 0)", **res}
+        s.attach_net(None)
+        net.close()
+
     out = {
         "metric": METRIC,
         "value": sec,
@@ -176,6 +207,7 @@ def main():
         "apply_ms": ms_apply,
         "apply_t_ms": ms_apply_t,
         "fp64_krylov": fp64,
+        "learned_mixed": learned,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_apply": alg_bytes,
@@ -184,6 +216,13 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, ~20-30 s)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(m, infos[-1]["inner_iters"])
+        # the FP64 oracle's own residual of the GPU solution (one CPU matvec)
+        from oracle.apply import Operator
+        xs = x.cpu().numpy()
+        op = Operator(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min)
+        b = np.zeros(op.n)
+        b[:m.dims[0] * m.dims[1] * m.dims[2]] = m.q00[0].astype(np.float64).reshape(-1)
+        out["oracle_rel_residual"] = float(np.linalg.norm(b - op.matvec(xs)) / np.linalg.norm(b))
     s.close()
     print(json.dumps(out), flush=True)
 

@@ -99,7 +99,21 @@ typedef struct {
   int use_guess;      /* 0: start from x = 0; 1: start from the x passed in    */
   int graph_iters;    /* Krylov iterations per captured HIP graph launch       */
   int variant;        /* PN_VARIANT_AUTO or PN_VARIANT_CGLS (see pn_solve)     */
+  int learned;        /* PN_LEARNED_* (needs a network, pn_attach_net in pn_nn.h) */
 } pn_solve_opts;
+
+/* Learned start and correction (PN_FP32_IR only; ignored without a network):
+ * OFF: plain solve.  GUESS: the initial iterate is s * u, u the network's
+ * prediction for the medium and Q, s the scalar minimising ||Q - s A u||_2
+ * (so the initial residual never exceeds ||Q||; use_guess = 0 only).
+ * GUESS_CORRECT: also, before every inner solve whose preceding step was not
+ * itself a correction, x += s * u with u the prediction for the current
+ * residual and s chosen the same way, kept only if it cuts the residual
+ * norm below 0.9 of its value (a flexible, residual-minimising preconditioner
+ * step of the refinement). */
+#define PN_LEARNED_OFF 0
+#define PN_LEARNED_GUESS 1
+#define PN_LEARNED_GUESS_CORRECT 2
 
 /* Krylov variant of the FP32 inner solve.  AUTO and CGLS: the residual-based
  * CGLS form (r <- r - alpha q fused into s = A^T r).  CG: CG on the normal
@@ -120,13 +134,15 @@ typedef struct {
   double seconds;           /* wall time of the solve                          */
   int nhistory;
   double history[PN_MAX_HISTORY]; /* FP64 relative residual per refinement step */
+  int learned_steps;        /* learned guesses / corrections applied           */
+  double learned_ratio;     /* residual reduction of the learned initial guess  */
 } pn_solve_info;
 
 int pn_abi_version(void);
 const char* pn_status_string(int status);
 
 /* Default options: FP32_IR, max_iter 200000, max_refine 40, inner_tol 1e-3,
- * use_guess 0, graph_iters 32. */
+ * use_guess 0, graph_iters 32, variant AUTO, learned OFF. */
 void pn_default_opts(pn_solve_opts* opts);
 
 /* Builds a solver context for truncation order 1 <= order <= 7 on `grid`
@@ -249,6 +265,10 @@ pn_status pn_batch_setup(int nprob, const pn_problem* probs, int nrhs, int tune,
 
 /* Layout of problem `prob` (as pn_layout_query). */
 pn_status pn_batch_layout(const pn_batch* batch, int prob, pn_layout* layout);
+/* Context of problem `prob` (geometry and medium, no Krylov workspace):
+ * valid for pn_layout_query, pn_net_features and pn_net_targets only; owned
+ * by the batch.  NULL on bad arguments. */
+pn_ctx* pn_batch_problem(const pn_batch* batch, int prob);
 /* Launch z-chunk used for problem `prob` (-1 on bad arguments). */
 int pn_batch_zchunk(const pn_batch* batch, int prob);
 /* Total unknowns over all systems. */

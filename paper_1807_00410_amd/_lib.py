@@ -40,13 +40,14 @@ class PnLayout(C.Structure):
 class PnSolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("max_iter", C.c_int), ("max_refine", C.c_int),
                 ("inner_tol", C.c_double), ("use_guess", C.c_int), ("graph_iters", C.c_int),
-                ("variant", C.c_int)]
+                ("variant", C.c_int), ("learned", C.c_int)]
 
 
 class PnSolveInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("outer_iters", C.c_int), ("inner_iters", C.c_int),
                 ("rel_residual", C.c_double), ("bnorm", C.c_double), ("seconds", C.c_double),
-                ("nhistory", C.c_int), ("history", C.c_double * PN_MAX_HISTORY)]
+                ("nhistory", C.c_int), ("history", C.c_double * PN_MAX_HISTORY),
+                ("learned_steps", C.c_int), ("learned_ratio", C.c_double)]
 
 
 class PnProblem(C.Structure):
@@ -89,6 +90,38 @@ SIGNATURES = [
     ("pn_batch_bench_apply", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     ("pn_batch_destroy", None, [C.c_void_p]),
     ("pn_batch_last_error", C.c_char_p, [C.c_void_p]),
+    ("pn_batch_problem", C.c_void_p, [C.c_void_p, C.c_int]),
+]
+
+_V = C.c_void_p
+_I = C.c_int
+# (name, restype, argtypes) of every exported symbol declared in include/pn_nn.h
+NN_SIGNATURES = [
+    ("pn_nn_conv3d", _I, [_I, _I, _I, _I, _V, _V, _V, _I, _I, _V, _V]),
+    ("pn_nn_conv3d_dgrad", _I, [_I, _I, _I, _I, _V, _V, _V, _V]),
+    ("pn_nn_conv3d_wgrad", _I, [_I, _I, _I, _I, _V, _V, _V, _V, _V]),
+    ("pn_nn_pool2", _I, [_I, _I, _I, _I, _V, _V, _V]),
+    ("pn_nn_pool2_bwd_add", _I, [_I, _I, _I, _I, _V, _V, _V, _V]),
+    ("pn_nn_up2_add", _I, [_I, _I, _I, _I, _V, _V, _V, _V]),
+    ("pn_nn_up2_bwd", _I, [_I, _I, _I, _I, _V, _V, _V]),
+    ("pn_nn_adam", _I, [_V, _V, _V, _V, C.c_longlong, C.c_longlong, C.c_float, C.c_double, C.c_double, C.c_float,
+                        _V]),
+    ("pn_nn_last_error", C.c_char_p, []),
+    ("pn_net_nparams", _I, []),
+    ("pn_net_create", _I, [C.c_ulonglong, _V, C.POINTER(_V)]),
+    ("pn_net_destroy", None, [_V]),
+    ("pn_net_last_error", C.c_char_p, [_V]),
+    ("pn_net_get_params", _I, [_V, _V, _V]),
+    ("pn_net_set_params", _I, [_V, _V]),
+    ("pn_net_save", _I, [_V, C.c_char_p]),
+    ("pn_net_load", _I, [_V, C.c_char_p]),
+    ("pn_net_forward", _I, [_V, _I, _I, _I, _I, _V, _V]),
+    ("pn_net_train_step", _I, [_V, _I, _I, _I, _I, _V, _V, _I, C.c_float, C.POINTER(C.c_double)]),
+    ("pn_net_set_stream", _I, [_V, _V]),
+    ("pn_net_grid", _I, [_V, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
+    ("pn_net_features", _I, [_V, _V, _V]),
+    ("pn_net_targets", _I, [_V, _V, _V]),
+    ("pn_attach_net", _I, [_V, _V]),
 ]
 
 _lib = None
@@ -104,7 +137,7 @@ def load(path=None):
         raise RuntimeError("libpn.so not found at %s: run `python -m paper_1807_00410_amd.build` "
                            "(there is no CPU fallback)" % p)
     lib = C.CDLL(p)
-    for name, res, args in SIGNATURES:
+    for name, res, args in SIGNATURES + NN_SIGNATURES:
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args

@@ -20,7 +20,7 @@ HIPCC_FLAGS = [
     "-Wno-unused-value", "-Wno-unused-result", "-fconstexpr-steps=200000000",
 ]
 
-SOURCES = ["pn_api.hip", "pn_batch.hip"] + ["pn_order_%d.hip" % n for n in range(1, 8)]
+SOURCES = ["pn_api.hip", "pn_batch.hip", "pn_nn.hip"] + ["pn_order_%d.hip" % n for n in range(1, 8)]
 
 
 def _run(cmd, verbose):

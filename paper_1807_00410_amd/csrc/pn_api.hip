@@ -16,6 +16,7 @@
 
 #include "../../include/pn.h"
 #include "pn_internal.h"
+#include "pn_learned.h"
 
 
 using namespace pn;
@@ -169,6 +170,8 @@ static void free_all(pn_ctx* c) {
   hipFree(c->s32); hipFree(c->p32); hipFree(c->q32); hipFree(c->d32); hipFree(c->b32); hipFree(c->x64);
   hipFree(c->s64); hipFree(c->p64); hipFree(c->q64); hipFree(c->d64);
   hipFree(c->st); hipFree(c->partials); hipFree(c->flag);
+  hipFree(c->net_x); hipFree(c->net_y); hipFree(c->u64); hipFree(c->w64); hipFree(c->absmax); hipFree(c->sq_part);
+  hipFree(c->st_net);
   if (c->st_host) hipHostFree(c->st_host);
   if (c->flag_host) hipHostFree(c->flag_host);
   if (c->ev_in) hipEventDestroy(c->ev_in);
@@ -201,6 +204,7 @@ extern "C" void pn_default_opts(pn_solve_opts* o) {
   o->use_guess = 0;
   o->graph_iters = 32;
   o->variant = PN_VARIANT_AUTO;
+  o->learned = PN_LEARNED_OFF;
 }
 
 extern "C" const char* pn_last_error(const pn_ctx* c) {
@@ -682,6 +686,155 @@ static pn_status build_graph(pn_ctx* c, int iters, T* d, T* p, T* q, T* s, T* r0
   return PN_OK;
 }
 
+// ------------------------------------------------------ learned network --
+static NetGeom net_geom(const pn_ctx* c, bool padded) {
+  NetGeom g;
+  std::memset(&g, 0, sizeof(g));
+  g.nx = c->nx; g.ny = c->ny; g.nz = c->nz;
+  g.nx8 = (c->nx + 7) / 8 * 8; g.ny8 = (c->ny + 7) / 8 * 8; g.nz8 = (c->nz + 7) / 8 * 8;
+  g.CX = c->nx + 2; g.CY = c->ny + 2;
+  g.nk = std::min(kNetOut, c->nc);
+  g.h = c->h;
+  for (int k = 0; k < g.nk; ++k) {
+    if (padded) {
+      g.base[k] = (long long)k * c->cs + ((long long)c->PY + 1) * c->PX + 1;
+      g.sy[k] = c->PX;
+      g.sz[k] = c->plane;
+    } else {
+      g.base[k] = c->off[k];
+      g.sy[k] = c->ext[k][0];
+      g.sz[k] = (long long)c->ext[k][0] * c->ext[k][1];
+    }
+  }
+  return g;
+}
+
+static pn_status ensure_small_net_bufs(pn_ctx* c) {
+  if (!c->absmax) PN_HIP(hipMalloc(&c->absmax, sizeof(unsigned)));
+  if (!c->sq_part) PN_HIP(hipMalloc(&c->sq_part, sizeof(double) * 1024));
+  return PN_OK;
+}
+
+static pn_status ensure_net_bufs(pn_ctx* c) {
+  pn_status e = ensure_small_net_bufs(c);
+  if (e != PN_OK) return e;
+  if (c->net_x) return PN_OK;
+  const NetGeom g = net_geom(c, true);
+  const long long v8 = (long long)g.nx8 * g.ny8 * g.nz8;
+  PN_HIP(hipMalloc(&c->net_x, sizeof(uint16_t) * v8 * nn::kC));
+  PN_HIP(hipMalloc(&c->net_y, sizeof(float) * v8 * nn::kC));
+  PN_HIP(hipMalloc(&c->u64, sizeof(double) * c->nv));
+  PN_HIP(hipMalloc(&c->w64, sizeof(double) * c->nv));
+  PN_HIP(hipMemsetAsync(c->w64, 0, sizeof(double) * c->nv, c->stream));
+  PN_HIP(hipMalloc(&c->st_net, sizeof(DevState)));
+  PN_HIP(hipMemsetAsync(c->st_net, 0, sizeof(DevState), c->stream));
+  PN_HIP(hipStreamSynchronize(c->stream));
+  return PN_OK;
+}
+
+static int cells_grid(const NetGeom& g) {
+  const long long n = (long long)g.nx * g.ny * g.nz;
+  long long b = (n + kBlock - 1) / kBlock;
+  return (int)std::max(1LL, std::min(b, 1024LL));
+}
+
+static pn_status launch_features(pn_ctx* c, const float* src, const NetGeom& g, uint16_t* x, hipStream_t s) {
+  PN_HIP(hipMemsetAsync(c->absmax, 0, sizeof(unsigned), s));
+  hipLaunchKernelGGL(k_src_absmax, dim3(cells_grid(g)), dim3(kBlock), 0, s, src, g, c->absmax);
+  const long long v8 = (long long)g.nx8 * g.ny8 * g.nz8;
+  hipLaunchKernelGGL(k_net_features, dim3(grid_for(v8)), dim3(kBlock), 0, s, (const float2*)c->med, src, g,
+                     (const unsigned*)c->absmax, x);
+  PN_HIP(hipGetLastError());
+  return PN_OK;
+}
+
+// u64 <- the network's prediction for the medium and a padded FP32 source.
+static pn_status net_predict(pn_ctx* c, const float* src_pad, hipStream_t s) {
+  const NetGeom g = net_geom(c, true);
+  pn_status e = launch_features(c, src_pad, g, c->net_x, s);
+  if (e != PN_OK) return e;
+  pn_net_set_stream(c->net, s);
+  e = pn_net_forward(c->net, 1, g.nx8, g.ny8, g.nz8, c->net_x, c->net_y);
+  if (e != PN_OK) return fail(c, e, std::string("network: ") + pn_net_last_error(c->net));
+  hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(c->nv)), dim3(kBlock), 0, s, c->u64, (long)c->nv, 0.0);
+  hipLaunchKernelGGL(k_net_to_lattice, dim3(grid_for((long long)g.nx * g.ny * g.nz * g.nk)), dim3(kBlock), 0, s,
+                     (const float*)c->net_y, g, c->u64);
+  PN_HIP(hipGetLastError());
+  return PN_OK;
+}
+
+// s minimising ||rhs - s A u64||_2 (rhs padded FP32) and the ratio of the
+// residual norms after / before, from ||A u||^2, ||rhs - A u||^2, ||rhs||^2.
+// The sums go through st_net: the Krylov scalars in st stay untouched, so a
+// rejected step leaves the refinement exactly as it was.
+static pn_status net_scale(pn_ctx* c, const float* rhs_pad, hipStream_t s, double* sopt, double* ratio) {
+  StencilArgs a = base_args(c);
+  a.x = c->u64; a.y = c->w64; a.partials = c->partials;
+  PN_HIP((launch_stencil<double, M_APPLY, double>(c, a, s)));
+  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kBlock), 0, s, c->st_net, c->partials, c->nblocks);
+  PN_HIP(hipMemcpyAsync(c->st_host, c->st_net, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  PN_HIP(hipStreamSynchronize(s));
+  const double au2 = c->st_host->rtrue2;
+  a = base_args(c);
+  a.x = c->u64; a.x2 = rhs_pad; a.y = c->r32[1]; a.partials = c->partials;
+  PN_HIP((launch_stencil<double, M_RESID, float>(c, a, s)));
+  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kBlock), 0, s, c->st_net, c->partials, c->nblocks);
+  PN_HIP(hipMemcpyAsync(c->st_host, c->st_net, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  PN_HIP(hipStreamSynchronize(s));
+  const double rr = c->st_host->rtrue2, bb = c->st_host->bb2;
+  *sopt = 0.0;
+  *ratio = 1.0;
+  if (au2 > 0.0 && bb > 0.0 && std::isfinite(au2) && std::isfinite(rr)) {
+    const double dot = 0.5 * (bb + au2 - rr);
+    *sopt = dot / au2;
+    *ratio = std::sqrt(std::max(0.0, bb - dot * dot / au2) / bb);
+  }
+  return PN_OK;
+}
+
+extern "C" pn_status pn_attach_net(pn_ctx* c, pn_net* net) {
+  if (!c) return PN_ERR_ARG;
+  c->net = net;
+  return PN_OK;
+}
+
+extern "C" pn_status pn_net_grid(const pn_ctx* c, int* nx8, int* ny8, int* nz8) {
+  if (!c || !nx8 || !ny8 || !nz8) return PN_ERR_ARG;
+  *nx8 = (c->nx + 7) / 8 * 8;
+  *ny8 = (c->ny + 7) / 8 * 8;
+  *nz8 = (c->nz + 7) / 8 * 8;
+  return PN_OK;
+}
+
+extern "C" pn_status pn_net_features(pn_ctx* c, const float* src, uint16_t* x) {
+  if (!c) return PN_ERR_ARG;
+  if (!src || !x) return fail(c, PN_ERR_ARG, "src or x is NULL");
+  pn_status e = ensure_small_net_bufs(c);
+  if (e != PN_OK) return e;
+  return launch_features(c, src, net_geom(c, false), x, c->stream);
+}
+
+extern "C" pn_status pn_net_targets(pn_ctx* c, const double* sol, uint16_t* t) {
+  if (!c) return PN_ERR_ARG;
+  if (!sol || !t) return fail(c, PN_ERR_ARG, "solution or t is NULL");
+  pn_status e = ensure_small_net_bufs(c);
+  if (e != PN_OK) return e;
+  const NetGeom g = net_geom(c, false);
+  const int nb = cells_grid(g);
+  hipLaunchKernelGGL(k_coef0_sumsq, dim3(nb), dim3(kBlock), 0, c->stream, sol, g, c->sq_part);
+  const long long n = (long long)g.nx8 * g.ny8 * g.nz8 * kNetOut;
+  hipLaunchKernelGGL(k_net_targets, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, sol, g,
+                     (const double*)c->sq_part, nb, t);
+  PN_HIP(hipGetLastError());
+  return PN_OK;
+}
+
+template <typename T>
+static const float* r0_as_float(const T* r) {
+  if constexpr (sizeof(T) == 4) return r;
+  else return nullptr;  // learned steps run in the FP32 solve only
+}
+
 // Iterative refinement around CGLS on the padded lattice.  b32 holds Q and
 // x64 the FP64 iterate on entry; x64 holds the result on exit.
 template <typename T>
@@ -723,6 +876,25 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
   int outer = 0;
   double rel = 0.0, bnorm = 0.0;
   if (info) info->nhistory = 0;
+  // learned start: x = s u with u the network's prediction for (medium, Q)
+  const bool learned = sizeof(T) == 4 && c->net != nullptr && o.learned != PN_LEARNED_OFF;
+  if (learned) {
+    pn_status e = ensure_net_bufs(c);
+    if (e != PN_OK) return e;
+  }
+  if (learned && !o.use_guess) {
+    double sc = 0.0, ratio = 1.0;
+    pn_status e = net_predict(c, c->b32, ss);
+    if (e == PN_OK) e = net_scale(c, c->b32, ss, &sc, &ratio);
+    if (e != PN_OK) return e;
+    if (ratio < 1.0 && std::isfinite(sc)) {
+      hipLaunchKernelGGL(k_axpby64, dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, c->x64, (const double*)c->u64, 0.0,
+                         sc, (long)c->nv);
+      PN_HIP(hipGetLastError());
+      if (info) { info->learned_steps += 1; info->learned_ratio = ratio; }
+    }
+  }
+  bool corrected = false;
   for (;;) {
     pn_status e = residual<T>(c, c->b32, c->x64, r0, ss);
     if (e != PN_OK) return e;
@@ -744,6 +916,22 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     if (rel <= tol) { result = PN_OK; break; }
     if (outer > o.max_refine || h.iters >= o.max_iter) { result = PN_ERR_NOT_CONVERGED; break; }
     if (h.breakdown) { result = PN_ERR_BREAKDOWN; break; }
+    // learned correction x += s u, u the prediction for the residual r0
+    if (learned && o.learned == PN_LEARNED_GUESS_CORRECT && !corrected) {
+      double sc = 0.0, ratio = 1.0;
+      pn_status e = net_predict(c, r0_as_float(r0), ss);
+      if (e == PN_OK) e = net_scale(c, r0_as_float(r0), ss, &sc, &ratio);
+      if (e != PN_OK) return e;
+      if (ratio < 0.9 && std::isfinite(sc)) {
+        hipLaunchKernelGGL(k_axpby64, dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, c->x64, (const double*)c->u64, 1.0,
+                           sc, (long)c->nv);
+        PN_HIP(hipGetLastError());
+        if (info) info->learned_steps += 1;
+        corrected = true;
+        continue;  // re-evaluate the FP64 residual
+      }
+    }
+    corrected = false;
     // inner solve  A d = r0  from d = 0
     double itol = o.inner_tol;
     if constexpr (sizeof(T) == 8) itol = 0.5 * tol / rel;  // FP64: go all the way
@@ -787,6 +975,8 @@ extern "C" pn_status pn_solve(pn_ctx* c, const float* rhs, double* x, double tol
   if (o.max_iter < 1 || o.max_refine < 0 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0))
     return fail(c, PN_ERR_ARG, "invalid solve options");
   if (o.precision != PN_FP32_IR && o.precision != PN_FP64) return fail(c, PN_ERR_ARG, "unknown precision");
+  if (o.learned < PN_LEARNED_OFF || o.learned > PN_LEARNED_GUESS_CORRECT)
+    return fail(c, PN_ERR_ARG, "unknown learned mode");
   if (info) std::memset(info, 0, sizeof(*info));
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t ss = c->sstream;

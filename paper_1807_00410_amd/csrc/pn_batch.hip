@@ -330,6 +330,11 @@ extern "C" pn_status pn_batch_layout(const pn_batch* b, int prob, pn_layout* lay
   return pn_layout_query(b->prob[prob], layout);
 }
 
+extern "C" pn_ctx* pn_batch_problem(const pn_batch* b, int prob) {
+  if (!b || prob < 0 || prob >= b->nprob) return nullptr;
+  return b->prob[prob];
+}
+
 extern "C" int pn_batch_zchunk(const pn_batch* b, int prob) {
   if (!b || prob < 0 || prob >= b->nprob) return -1;
   return b->prob[prob]->zchunk;

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "../../include/pn.h"
+#include "../../include/pn_nn.h"
 #include "pn_launch.h"
 
 namespace pn {  // instantiated in pn_order_N.hip
@@ -86,6 +87,15 @@ struct pn_ctx {
   size_t lds_bytes = 0, lds_max = 0;
   hipGraphExec_t gexec_cg = nullptr;  // captured CG-on-normal-equations iterations
   int giters_cg = 0;
+  // learned initial guess / correction (pn_attach_net)
+  pn_net* net = nullptr;
+  uint16_t* net_x = nullptr;   // network input [cells8][32] bfloat16
+  float* net_y = nullptr;      // network output [cells8][32]
+  double* u64 = nullptr;       // network prediction on the padded lattice
+  double* w64 = nullptr;       // A u
+  unsigned* absmax = nullptr;  // max |source| (float bits)
+  double* sq_part = nullptr;   // FP64 partial sums (targets)
+  DevState* st_net = nullptr;  // scalars of the learned step's line search (kept apart from st)
   std::string err;
 };
 

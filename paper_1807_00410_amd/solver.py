@@ -112,6 +112,28 @@ class Solver:
         self._check(self.lib.pn_bench_apply(self.ctx, int(iters), int(transpose), C.byref(ms)))
         return ms.value
 
+    def attach_net(self, net):
+        """Attaches a paper_1807_00410_amd.net.Net (None detaches)."""
+        self._net = net
+        self._check(self.lib.pn_attach_net(self.ctx, net.n if net is not None else None))
+
+    def net_grid(self):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        self._check(self.lib.pn_net_grid(self.ctx, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def net_features(self, src):
+        nx8, ny8, nz8 = self.net_grid()
+        x = torch.empty((1, nz8, ny8, nx8, 32), dtype=torch.bfloat16, device=src.device)
+        self._check(self.lib.pn_net_features(self.ctx, _ptr(src, torch.float32), C.c_void_p(x.data_ptr())))
+        return x
+
+    def net_targets(self, sol):
+        nx8, ny8, nz8 = self.net_grid()
+        t = torch.empty((1, nz8, ny8, nx8, 16), dtype=torch.bfloat16, device=sol.device)
+        self._check(self.lib.pn_net_targets(self.ctx, _ptr(sol, torch.float64), C.c_void_p(t.data_ptr())))
+        return t
+
     def autotune(self, iters=10):
         """Times the candidate launch z-chunks, keeps the fastest (also in the
         process-wide tune cache).  Returns (zchunk, ms per apply)."""
@@ -134,11 +156,13 @@ class Solver:
         return tx.value, ty.value, z.value
 
     def solve(self, rhs, x=None, tol=1e-8, precision="fp32_ir", max_iter=200000, max_refine=40,
-              inner_tol=1e-3, use_guess=False, graph_iters=32, variant="auto", raise_on_fail=True):
-        """Solves A x = rhs.  Returns (x, info dict)."""
+              inner_tol=1e-3, use_guess=False, graph_iters=32, variant="auto", learned="off", raise_on_fail=True):
+        """Solves A x = rhs.  learned: "off", "guess" or "guess+correct" (needs
+        attach_net).  Returns (x, info dict)."""
         if x is None:
             x = torch.zeros(self.n, dtype=torch.float64, device=rhs.device)
         opts = _opts(self.lib, precision, max_iter, max_refine, inner_tol, use_guess, graph_iters, variant)
+        opts.learned = {"off": 0, "guess": 1, "guess+correct": 2}[learned]
         info = L.PnSolveInfo()
         rc = self.lib.pn_solve(self.ctx, _ptr(rhs, torch.float32), _ptr(x, torch.float64), float(tol),
                                C.byref(opts), C.byref(info))
@@ -172,7 +196,8 @@ def _opts(lib, precision, max_iter, max_refine, inner_tol, use_guess, graph_iter
 def _info(rc, info):
     return dict(status=rc, outer_iters=info.outer_iters, inner_iters=info.inner_iters,
                 rel_residual=info.rel_residual, bnorm=info.bnorm, seconds=info.seconds,
-                history=[info.history[i] for i in range(info.nhistory)])
+                history=[info.history[i] for i in range(info.nhistory)],
+                learned_steps=info.learned_steps, learned_ratio=info.learned_ratio)
 
 
 class Batch:
@@ -218,6 +243,26 @@ class Batch:
 
     def zchunk(self, prob):
         return self.lib.pn_batch_zchunk(self.b, int(prob))
+
+    def net_features(self, prob, src):
+        """Network input of problem `prob` for a packed FP32 source vector."""
+        ctx = self.lib.pn_batch_problem(self.b, int(prob))
+        g = [C.c_int() for _ in range(3)]
+        self._check(self.lib.pn_net_grid(ctx, *[C.byref(v) for v in g]))
+        nx8, ny8, nz8 = (v.value for v in g)
+        x = torch.empty((1, nz8, ny8, nx8, 32), dtype=torch.bfloat16, device=src.device)
+        self._check(self.lib.pn_net_features(ctx, _ptr(src, torch.float32), C.c_void_p(x.data_ptr())))
+        return x
+
+    def net_targets(self, prob, sol, out=None):
+        """Training target of problem `prob` for a packed FP64 solution."""
+        ctx = self.lib.pn_batch_problem(self.b, int(prob))
+        g = [C.c_int() for _ in range(3)]
+        self._check(self.lib.pn_net_grid(ctx, *[C.byref(v) for v in g]))
+        nx8, ny8, nz8 = (v.value for v in g)
+        t = out if out is not None else torch.empty((1, nz8, ny8, nx8, 16), dtype=torch.bfloat16, device=sol.device)
+        self._check(self.lib.pn_net_targets(ctx, _ptr(sol, torch.float64), C.c_void_p(t.data_ptr())))
+        return t
 
     def close(self):
         if getattr(self, "b", None):

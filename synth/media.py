@@ -136,16 +136,19 @@ def config_p1_homogeneous(n=16):
                   _f32(np.full((n, n, n), 0.9)), 0.0, 0.0, [_f32(q)])
 
 
-def config_p3_fbm(n=64, seed=1, order=3, sigma_t_min=1.0, g=0.3):
+def config_p3_fbm(n=64, seed=1, order=3, sigma_t_min=1.0, g=0.3, nrhs=1):
     """P3, n^3: sigma_t = 50 * fBm, albedo ~ U[0.8, 0.99] per cell, HG g = 0.3,
-    emission a Gaussian blob of std 4 cells at a seeded centre."""
+    emission a Gaussian blob of std 4 cells at a seeded centre (nrhs > 1: more
+    blobs at further seeded centres, one per right-hand side)."""
     rng = np.random.default_rng(seed)
     dims = (n, n, n)
     st = 50.0 * fbm(dims, seed)
     alb = rng.uniform(0.8, 0.99, size=(n, n, n))
-    c = rng.uniform(0.3, 0.7, size=3)
-    q = gaussian_blob(dims, c, 4.0 / n)
-    return Medium("p%d_fbm_%d_s%d" % (order, n, seed), order, dims, _f32(st), _f32(alb), g, sigma_t_min, [_f32(q)])
+    qs = []
+    for _ in range(nrhs):
+        c = rng.uniform(0.3, 0.7, size=3)
+        qs.append(_f32(gaussian_blob(dims, c, 4.0 / n)))
+    return Medium("p%d_fbm_%d_s%d" % (order, n, seed), order, dims, _f32(st), _f32(alb), g, sigma_t_min, qs)
 
 
 def config_p5_nebula(n=128, seed=3, g=0.0, order=5, sigma_t_min=1.0, nblobs=32):

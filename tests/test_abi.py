@@ -27,8 +27,13 @@ def lib():
 def test_every_declared_symbol_is_exported(lib):
     names = _declared("pn.h")
     assert "pn_setup" in names and "pn_solve" in names and "pn_apply" in names
-    for n in names:
+    nn = _declared("pn_nn.h")
+    assert "pn_nn_conv3d" in nn and "pn_net_train_step" in nn
+    from paper_1807_00410_amd import _lib as L
+    bound = {s[0] for s in L.SIGNATURES + L.NN_SIGNATURES}
+    for n in names + nn:
         assert hasattr(lib, n), n
+        assert n in bound, n  # the Python binding declares it too
 
 
 def test_abi_version(lib):
@@ -108,3 +113,15 @@ def test_tune_cache_file_roundtrip_on_host(lib, tmp_path):
     assert lib.pn_autotune(None, 3, None, None) == L.PN_ERR_ARG
     lib.pn_tune_cache_clear()
     assert lib.pn_tune_cache_size() == 0
+
+
+def test_net_rejects_bad_arguments_on_host(lib):
+    from paper_1807_00410_amd import _lib as L
+    assert lib.pn_net_nparams() == 15 * (27 * 32 * 32 + 32)
+    assert lib.pn_net_create(0, None, None) == L.PN_ERR_ARG
+    assert lib.pn_net_forward(None, 1, 8, 8, 8, None, None) == L.PN_ERR_ARG
+    assert lib.pn_nn_conv3d(0, 8, 8, 8, None, None, None, 0, 0, None, None) == L.PN_ERR_ARG
+    assert lib.pn_nn_pool2(1, 7, 8, 8, C.c_void_p(16), C.c_void_p(16), None) == L.PN_ERR_ARG
+    assert lib.pn_nn_adam(None, None, None, None, 10, 1, 1e-3, 0.9, 0.999, 1e-8, None) == L.PN_ERR_ARG
+    assert lib.pn_nn_last_error()
+    lib.pn_net_destroy(None)

@@ -1,0 +1,131 @@
+"""GPU tests of the solver <-> network connection: the feature and target
+tensors against their plain definitions, and the learned initial guess /
+correction inside pn_solve (which may only ever shrink the residual and must
+leave the converged result within the oracle tolerance)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.assemble import assemble, rhs_isotropic
+from oracle.solve import cgls, direct
+from synth import config_p3_fbm, config_small
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_1807_00410_amd", "weights", "unet_p3.bin")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def solver(m):
+    from paper_1807_00410_amd.solver import Solver
+    return Solver(m.order, m.dims, dev(m.sigma_t), dev(m.albedo), g=m.g, sigma_t_min=m.sigma_t_min, bc=m.bc)
+
+
+def bf16_host(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def test_features_and_targets_definitions():
+    m = config_small(3, (11, 9, 13), seed=3)
+    s = solver(m)
+    nx, ny, nz = m.dims
+    assert s.net_grid() == (16, 16, 16)
+    rhs = s.rhs_from_q00(dev(m.q00[0]))
+    x = bf16_host(s.net_features(rhs))[0]
+    st = np.maximum(m.sigma_t.astype(np.float64), np.float32(m.sigma_t_min))
+    h = 1.0 / nx
+    q = m.q00[0].astype(np.float64)
+    f = np.zeros((16, 16, 16, 3))
+    f[:nz, :ny, :nx, 0] = st * h
+    f[:nz, :ny, :nx, 1] = st * (1.0 - m.albedo) * h
+    f[:nz, :ny, :nx, 2] = q / np.abs(q).max()
+    assert np.all(np.abs(x[..., :3] - f) <= 2.0 ** -7 * np.abs(f) + 1e-7)
+    assert np.all(x[..., 3:] == 0.0)
+    # a solution-shaped vector: target channel k = coefficient k at the cell's lattice point / rms(L00)
+    lay = s.layout
+    u = np.random.default_rng(1).normal(size=s.n)
+    t = bf16_host(s.net_targets(dev(u, torch.float64)))[0]
+    rms = np.sqrt(np.mean(u[:lay.offset[1]] ** 2))
+    ref = np.zeros((16, 16, 16, 16))
+    for k in range(16):
+        ex, ey, ez = lay.ext[k]
+        blk = u[lay.offset[k]:lay.offset[k + 1]].reshape(ez, ey, ex)
+        ref[:nz, :ny, :nx, k] = blk[:nz, :ny, :nx] / rms
+    assert np.all(np.abs(t - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-12)
+    s.close()
+
+
+def _oracle(m):
+    A, lay = assemble(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min, bc=m.bc)
+    b = rhs_isotropic(lay, m.q00[0])
+    if A.shape[0] <= 20000:
+        return A, b, direct(A, b)
+    AT = A.T.tocsr()
+    u, _ = cgls(lambda v: A @ v, lambda v: AT @ v, b, tol=1e-13)
+    return A, b, u
+
+
+@pytest.mark.parametrize("mode", ["guess", "guess+correct"])
+def test_learned_modes_keep_the_solution(mode):
+    # an untrained network: the residual-minimising scale keeps every learned
+    # step harmless, and the solve reaches the same answer
+    from paper_1807_00410_amd.net import Net
+    m = config_p3_fbm(n=16, seed=21, order=3)
+    A, b, u = _oracle(m)
+    s = solver(m)
+    net = Net(seed=3)
+    s.attach_net(net)
+    rhs = s.rhs_from_q00(dev(m.q00[0]))
+    x, info = s.solve(rhs, tol=1e-8, learned=mode)
+    xs = x.cpu().numpy()
+    res = np.linalg.norm(b - A @ xs) / np.linalg.norm(b)
+    err = np.linalg.norm(xs - u) / np.linalg.norm(u)
+    print("%s: iters=%d outer=%d learned_steps=%d ratio=%.3f res=%.3g err=%.3g" % (
+        mode, info["inner_iters"], info["outer_iters"], info["learned_steps"], info["learned_ratio"], res, err))
+    assert info["status"] == 0 and res <= 1.01e-8 and err <= 1e-5
+    assert info["learned_ratio"] <= 1.0
+    assert all(h2 <= 1.0 for h2 in info["history"][:1])
+    s.attach_net(None)
+    x2, info2 = s.solve(rhs, tol=1e-8, learned=mode)  # detached: the plain solve
+    assert info2["learned_steps"] == 0
+    s.close()
+    net.close()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained weights in the tree")
+def test_trained_network_gain_on_held_out_medium():
+    # ablation: the trained network as initial guess (and correction) against
+    # the plain solve on a held-out P3 64^3 fBm medium (a seed outside the
+    # training range)
+    from paper_1807_00410_amd.net import Net
+    m = config_p3_fbm(n=64, seed=90001, order=3)
+    s = solver(m)
+    rhs = s.rhs_from_q00(dev(m.q00[0]))
+    x0, plain = s.solve(rhs, tol=1e-8)
+    net = Net(seed=0)
+    net.load(WEIGHTS)
+    s.attach_net(net)
+    x1, lg = s.solve(rhs, tol=1e-8, learned="guess")
+    x2, lc = s.solve(rhs, tol=1e-8, learned="guess+correct")
+    for name, d in (("plain", plain), ("guess", lg), ("guess+correct", lc)):
+        print("%-14s iters=%5d outer=%2d learned=%d ratio=%.3f t=%.3fs" % (
+            name, d["inner_iters"], d["outer_iters"], d["learned_steps"], d["learned_ratio"], d["seconds"]))
+        assert d["status"] == 0
+    # the trained guess must beat x = 0 clearly, and not cost iterations
+    assert lg["learned_ratio"] < 0.5
+    assert lg["inner_iters"] <= plain["inner_iters"]
+    d = (x1 - x0).norm().item() / x0.norm().item()
+    assert d < 1e-6
+    s.close()
+    net.close()
