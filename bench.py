@@ -75,6 +75,65 @@ def cpu_baseline(medium, gpu_iters):
             "seconds_per_iteration": t_iter}
 
 
+def bench_batch(args):
+    """The batched workload: 48 seeded media (n in {32,48,64,96}, orders
+    P1/P3/P5/P7, fBm sigma_t in [0,100], albedo 0.9, g = 0), 8 Gaussian
+    emission fields each, solved together to tol with autotuned launch shapes.
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+    from synth import config_batch
+    from paper_1807_00410_amd.solver import Batch
+
+    t0 = time.perf_counter()
+    media = config_batch(seed=7, nmedia=args.batch_media, nrhs=8)
+    print("[bench] %d media generated in %.1fs" % (len(media), time.perf_counter() - t0), file=sys.stderr, flush=True)
+    probs = [(m.order, m.dims, torch.as_tensor(m.sigma_t).cuda(), torch.as_tensor(m.albedo).cuda(), m.g,
+              m.sigma_t_min, m.bc) for m in media]
+    t0 = time.perf_counter()
+    B = Batch(probs, 8, tune=True)
+    t_setup = time.perf_counter() - t0
+    rhs = []
+    for p, m in enumerate(media):
+        lay = B.layouts[p]
+        for q in m.q00:
+            b = torch.zeros(lay.n, dtype=torch.float32, device="cuda")
+            b[lay.offset[0]:lay.offset[1]] = torch.as_tensor(q).cuda().reshape(-1)
+            rhs.append(b)
+    xs = [torch.zeros(B.layouts[i // 8].n, dtype=torch.float64, device="cuda") for i in range(len(rhs))]
+    print("[bench] batch set up in %.1fs: %d systems, %d unknowns" % (t_setup, len(rhs), B.unknowns),
+          file=sys.stderr, flush=True)
+    ms_apply = B.bench_apply(iters=5)
+    cells = sum(m.dims[0] * m.dims[1] * m.dims[2] for m in media)
+    alg = 8 * B.unknowns + 8 * cells  # every system's x and y once; each medium once per tile
+    print("[bench] batched apply %.3f ms (%.0f GB/s algorithmic)" % (ms_apply, alg / ms_apply / 1e6),
+          file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    xs, infos = B.solve(rhs, x=xs, tol=args.tol, inner_tol=args.inner_tol, raise_on_fail=False)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t1
+    iters = np.array([d["inner_iters"] for d in infos])
+    status = [d["status"] for d in infos]
+    unk_it = sum(B.layouts[i // 8].n * int(iters[i]) for i in range(len(infos)))
+    print("[bench] batched solve %.2fs, iterations min/mean/max %d/%.0f/%d, %d converged" % (
+        sec, iters.min(), iters.mean(), iters.max(), status.count(0)), file=sys.stderr, flush=True)
+    out = {
+        "metric": "batched solve: unknown-iterations per second (48 media x 8 RHS to tol)",
+        "value": unk_it / sec, "unit": "unknown-iterations/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "%d seeded fBm media, n in {32,48,64,96}, P1/P3/P5/P7, 8 RHS each, vacuum, tol %g"
+                               % (len(media), args.tol), "systems": len(rhs), "unknowns": B.unknowns},
+        "solve_seconds": sec, "setup_seconds": t_setup, "converged": status.count(0),
+        "iters_min": int(iters.min()), "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
+        "batched_apply_ms": ms_apply, "batched_apply_algorithmic_GBs": alg / ms_apply / 1e6,
+        "zchunks": [B.zchunk(p) for p in range(len(media))],
+    }
+    B.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,17 +143,22 @@ def main():
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--g", type=float, default=0.0)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--inner-tol", type=float, default=1e-3)
+    ap.add_argument("--inner-tol", type=float, default=1e-2)
     ap.add_argument("--apply-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the pure FP64 Krylov comparison solve")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned + mixed-precision solve")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1807_00410_amd", "weights", "unet_p3.bin"))
+    ap.add_argument("--workload", choices=("p5", "batch"), default="p5")
+    ap.add_argument("--batch-media", type=int, default=48)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     import numpy as np
     import torch
@@ -109,6 +173,8 @@ def main():
     al = torch.as_tensor(m.albedo).to(dev)
     q00 = torch.as_tensor(m.q00[0]).to(dev)
     s = Solver(m.order, m.dims, st, al, g=m.g, sigma_t_min=m.sigma_t_min)
+    zchunk, ms_tuned = s.autotune(10)  # launch shape from the project's autotuner
+    print("[bench] autotuned zchunk %d (%.4f ms per apply)" % (zchunk, ms_tuned), file=sys.stderr, flush=True)
     rhs = s.rhs_from_q00(q00)
     x = torch.zeros(s.n, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
@@ -153,6 +219,19 @@ def main():
                 "status": i64["status"]}
         print("[bench] fp64 CGLS: %.3fs iters %d" % (i64["seconds"], i64["inner_iters"]), file=sys.stderr,
               flush=True)
+
+    # FP32 Krylov without refinement: one inner CGLS asked for the full
+    # reduction (FP64 dots, FP32 vectors); its FP64 true residual shows where
+    # FP32 alone stalls
+    fp32_single = None
+    if not args.no_fp64:
+        xx = torch.zeros_like(x)
+        _, i32 = s.solve(rhs, x=xx, tol=args.tol, inner_tol=1e-9, max_refine=1, max_iter=8000,
+                         raise_on_fail=False)
+        fp32_single = {"seconds": i32["seconds"], "iters": i32["inner_iters"], "rel_residual": i32["rel_residual"],
+                       "status": i32["status"]}
+        print("[bench] fp32 CGLS without refinement: %.3fs iters %d rel %.3g" % (
+            i32["seconds"], i32["inner_iters"], i32["rel_residual"]), file=sys.stderr, flush=True)
 
     learned = None
     if not args.no_learned and os.path.exists(args.weights):
@@ -199,7 +278,8 @@ def main():
         "config": {"workload": "P%d nebula %d^3 (32 Gaussian blobs x fBm, sigma_t in [0,200], albedo 0.95, "
                                "g=%g, 2 point sources), vacuum boundary, tol %g"
                                % (m.order, args.n, m.g, args.tol),
-                   "unknowns": s.n, "solver": "FP32 CGLS + FP64 dots/refinement (plain)"},
+                   "unknowns": s.n, "solver": "FP32 CGLS + FP64 dots/refinement (plain)",
+                   "inner_tol": args.inner_tol, "zchunk": zchunk},
         "iters": infos[-1]["inner_iters"],
         "outer_iters": infos[-1]["outer_iters"],
         "rel_residual": infos[-1]["rel_residual"],
@@ -207,6 +287,7 @@ def main():
         "apply_ms": ms_apply,
         "apply_t_ms": ms_apply_t,
         "fp64_krylov": fp64,
+        "fp32_krylov_no_refinement": fp32_single,
         "learned_mixed": learned,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -104,8 +104,9 @@ typedef struct {
 
 /* Learned start and correction (PN_FP32_IR only; ignored without a network):
  * OFF: plain solve.  GUESS: the initial iterate is s * u, u the network's
- * prediction for the medium and Q, s the scalar minimising ||Q - s A u||_2
- * (so the initial residual never exceeds ||Q||; use_guess = 0 only).
+ * prediction for the medium and Q, s the scalar minimising ||Q - s A u||_2,
+ * kept only if it cuts the residual below 0.9 ||Q|| (use_guess = 0 only;
+ * info->learned_ratio reports the ratio either way).
  * GUESS_CORRECT: also, before every inner solve whose preceding step was not
  * itself a correction, x += s * u with u the prediction for the current
  * residual and s chosen the same way, kept only if it cuts the residual
@@ -135,13 +136,13 @@ typedef struct {
   int nhistory;
   double history[PN_MAX_HISTORY]; /* FP64 relative residual per refinement step */
   int learned_steps;        /* learned guesses / corrections applied           */
-  double learned_ratio;     /* residual reduction of the learned initial guess  */
+  double learned_ratio;     /* residual ratio the learned initial guess offers  */
 } pn_solve_info;
 
 int pn_abi_version(void);
 const char* pn_status_string(int status);
 
-/* Default options: FP32_IR, max_iter 200000, max_refine 40, inner_tol 1e-3,
+/* Default options: FP32_IR, max_iter 200000, max_refine 40, inner_tol 1e-2,
  * use_guess 0, graph_iters 32, variant AUTO, learned OFF. */
 void pn_default_opts(pn_solve_opts* opts);
 

@@ -106,9 +106,8 @@ pn_status pn_net_grid(const pn_ctx* ctx, int* nx8, int* ny8, int* nz8);
 pn_status pn_net_features(pn_ctx* ctx, const float* src, uint16_t* x);
 /* Training target for a solution (device FP64 vector, packed layout):
  * t [nz8][ny8][nx8][16] bfloat16, channel k = coefficient k (bands l <= 3) at
- * the lattice point with the cell's indices, divided by the root mean square
- * of coefficient 0 over the cells; zero where there is none.  On the
- * context's stream. */
+ * the lattice point with the cell's indices, divided by the largest |L00|
+ * over the cells; zero where there is none.  On the context's stream. */
 pn_status pn_net_targets(pn_ctx* ctx, const double* solution, uint16_t* t);
 /* Attaches a network to a solver context (NULL detaches); pn_solve uses it
  * as opts->learned asks.  The network must outlive the attachment. */

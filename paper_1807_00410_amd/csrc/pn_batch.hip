@@ -417,8 +417,6 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
   B_HIP(hipMemcpyAsync(b->st, b->st_host, sizeof(DevState) * b->nsys, hipMemcpyHostToDevice, ss));
   std::vector<int> outer(b->nsys, 0), status(b->nsys, PN_ERR_NOT_CONVERGED);
   std::vector<double> rel(b->nsys, 0.0), bnorm(b->nsys, 0.0);
-  double itol = o.inner_tol;
-  if (itol >= 1.0) itol = 0.5;
   for (;;) {
     // r = Q - A x in FP64 for every running system
     B_HIP(stencil_all(b, K_F64_RESID32, roles(b, BV_X64, BV_B, BV_R0, -1, 1.0, 0), ss));
@@ -451,6 +449,9 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
         status[i] = s;
         h.frozen = 1;
       } else {
+        // as pn_solve: inner_tol, but no further than the outer tolerance needs
+        double itol = std::max(o.inner_tol, 0.3 * tol / rel[i]);
+        if (itol >= 1.0) itol = 0.5;
         h.itol2 = itol * itol;
         ++nactive;
       }

@@ -94,7 +94,7 @@ struct pn_ctx {
   double* u64 = nullptr;       // network prediction on the padded lattice
   double* w64 = nullptr;       // A u
   unsigned* absmax = nullptr;  // max |source| (float bits)
-  double* sq_part = nullptr;   // FP64 partial sums (targets)
+  double* sq_part = nullptr;   // FP64 block partials (targets)
   DevState* st_net = nullptr;  // scalars of the learned step's line search (kept apart from st)
   std::string err;
 };

@@ -39,8 +39,8 @@ __device__ __forceinline__ long long lat(const NetGeom& g, int k, int x, int y, 
   return g.base[k] + (long long)z * g.sz[k] + (long long)y * g.sy[k] + x;
 }
 
-// max |v| over the cells of coefficient 0 of an FP32 lattice vector
-// (one block; result as float bits through atomicMax on non-negative floats).
+// max |v| over the cells of coefficient 0 of an FP32 lattice vector (float
+// bits combined with atomicMax, valid for non-negative floats; *out zeroed first).
 static __global__ void __launch_bounds__(kBlock) k_src_absmax(const float* __restrict__ v, const NetGeom g,
                                                               unsigned* __restrict__ out) {
   float m = 0.f;
@@ -92,36 +92,34 @@ static __global__ void __launch_bounds__(kBlock) k_net_to_lattice(const float* _
   }
 }
 
-// Sum of squares of coefficient 0 of an FP64 lattice vector at the cells
-// (FP64 block partials).
-static __global__ void __launch_bounds__(kBlock) k_coef0_sumsq(const double* __restrict__ u, const NetGeom g,
-                                                               double* __restrict__ partial) {
+// max |coefficient 0| of an FP64 lattice vector over the cells (FP64 block
+// partial maxima).
+static __global__ void __launch_bounds__(kBlock) k_coef0_absmax(const double* __restrict__ u, const NetGeom g,
+                                                                double* __restrict__ partial) {
   __shared__ double red[kBlock];
   double s = 0.0;
   const long long n = (long long)g.nx * g.ny * g.nz;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
-    const double v = u[lat(g, 0, x, y, z)];
-    s += v * v;
+    s = fmax(s, fabs(u[lat(g, 0, x, y, z)]));
   }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 // Training target [cells8][kNetOut] (bfloat16) from an FP64 lattice
-// solution, scaled by 1 / rms(coefficient 0) (sum of squares from `partial`).
+// solution, divided by max |coefficient 0| (block maxima in `partial`).
 static __global__ void __launch_bounds__(kBlock) k_net_targets(const double* __restrict__ u, const NetGeom g,
                                                                const double* __restrict__ partial, int nparts,
                                                                uint16_t* __restrict__ t) {
-  double ss = 0.0;
-  for (int p = 0; p < nparts; ++p) ss += partial[p];
-  const double ncell = (double)g.nx * g.ny * g.nz;
-  const double sc = ss > 0.0 ? 1.0 / sqrt(ss / ncell) : 0.0;
+  double mx = 0.0;
+  for (int p = 0; p < nparts; ++p) mx = fmax(mx, partial[p]);
+  const double sc = mx > 0.0 ? 1.0 / mx : 0.0;
   const long long n = (long long)g.nx8 * g.ny8 * g.nz8 * kNetOut;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     const int k = (int)(i % kNetOut);

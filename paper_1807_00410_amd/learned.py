@@ -1,8 +1,9 @@
 """Training and evaluation of the learned initial guess / preconditioner.
 
 The data are pairs the solver itself produces: seeded P3 fBm media on a 64^3
-grid (sigma_t = 50 fBm, albedo ~ U[0.8, 0.99], g = 0.3, Gaussian emission
-blobs of std 4 cells), each with several emission fields, solved together by
+grid (the P3 generator: sigma_t = 50 fBm, albedo ~ U[0.8, 0.99], g = 0.3,
+Gaussian emission blobs of std 4 cells; or, with --data mixed, a per-medium
+extinction scale and point / narrow sources), 8 emission fields each, solved together by
 the batched solver; the network input and the target of every solution come
 from the library (pn_net_features / pn_net_targets) and the network is
 trained by the library's own forward / backward / Adam kernels.  This module
@@ -27,7 +28,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from synth import config_p3_fbm, config_p5_nebula  # noqa: E402
+from synth import config_p3_fbm, config_p3_train, config_p5_nebula  # noqa: E402
 
 from .net import Net  # noqa: E402
 from .solver import Batch, Solver  # noqa: E402
@@ -36,7 +37,9 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "u
 
 
 def _medium(args):
-    n, seed, nrhs = args
+    n, seed, nrhs, data = args
+    if data == "mixed":
+        return config_p3_train(n=n, seed=seed, nrhs=nrhs)
     return config_p3_fbm(n=n, seed=seed, order=3, nrhs=nrhs)
 
 
@@ -44,7 +47,7 @@ def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a)).cuda()
 
 
-def generate(n=64, nmedia=250, nrhs=8, seed0=1000, chunk=16, tol=1e-5, workers=12, log=print):
+def generate(n=64, nmedia=250, nrhs=8, seed0=1000, chunk=16, tol=1e-5, workers=12, data="p3", log=print):
     """Solves nmedia x nrhs P3 problems; returns (X, T, stats): X [N, n, n, n,
     32] and T [N, n, n, n, 16] bfloat16 on the GPU, sample order shuffled by
     medium."""
@@ -54,7 +57,7 @@ def generate(n=64, nmedia=250, nrhs=8, seed0=1000, chunk=16, tol=1e-5, workers=1
     t0 = time.time()
     iters = []
     with ProcessPoolExecutor(max_workers=workers) as ex:
-        media_iter = ex.map(_medium, [(n, seed0 + i, nrhs) for i in range(nmedia)])
+        media_iter = ex.map(_medium, [(n, seed0 + i, nrhs, data) for i in range(nmedia)])
         k = 0
         solve_s = 0.0
         for c0 in range(0, nmedia, chunk):
@@ -108,7 +111,7 @@ def train(net, X, T, epochs=10, batch=4, lr=2e-3, val=16, seed=0, log=print):
             step += 1
         vl = [net.train_step(X[i:i + 1], T[i:i + 1], 0.0) for i in range(N, N + val)]
         hist.append((float(np.mean(losses)), float(np.mean(vl))))
-        log("  epoch %2d: train loss %.4f  validation loss %.4f  (%.1f s)" % (ep, hist[-1][0], hist[-1][1],
+        log("  epoch %2d: train loss %.3e  validation loss %.3e  (%.1f s)" % (ep, hist[-1][0], hist[-1][1],
                                                                             time.time() - t0))
     return hist
 
@@ -147,10 +150,13 @@ def main():
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval", action="store_true", help="evaluate on held-out P3 96^3 and P5 128^3 media")
+    ap.add_argument("--data", choices=("p3", "mixed"), default="p3",
+                    help="p3: the P3 fBm generator (sigma_t 50 fBm, blobs of std 4 cells); mixed: per-medium "
+                         "extinction scale and point / narrow sources")
     args = ap.parse_args()
     log = lambda *a: print(*a, flush=True)
     log("generating %d x %d P3 %d^3 samples" % (args.media, args.nrhs, args.n))
-    X, T, st = generate(n=args.n, nmedia=args.media, nrhs=args.nrhs, log=log)
+    X, T, st = generate(n=args.n, nmedia=args.media, nrhs=args.nrhs, data=args.data, log=log)
     net = Net(seed=1)
     log("training: %d epochs, batch %d, lr %g" % (args.epochs, args.batch, args.lr))
     train(net, X, T, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)

@@ -151,6 +151,29 @@ def config_p3_fbm(n=64, seed=1, order=3, sigma_t_min=1.0, g=0.3, nrhs=1):
     return Medium("p%d_fbm_%d_s%d" % (order, n, seed), order, dims, _f32(st), _f32(alb), g, sigma_t_min, qs)
 
 
+def config_p3_train(n=64, seed=1000, nrhs=8, order=3, sigma_t_min=1.0, g=0.3):
+    """Training media for the learned guess: the P3 fBm medium with its
+    extinction scale drawn per medium (sigma_t = S * fBm, S ~ U[25, 200]) and
+    emission of mixed widths per right-hand side: a single-cell point source
+    (one in four) or a Gaussian blob of std U[0.7, 4] cells."""
+    rng = np.random.default_rng(seed)
+    dims = (n, n, n)
+    scale = rng.uniform(25.0, 200.0)
+    st = scale * fbm(dims, seed)
+    alb = rng.uniform(0.8, 0.99, size=(n, n, n))
+    qs = []
+    for _ in range(nrhs):
+        if rng.uniform() < 0.25:
+            q = np.zeros((n, n, n))
+            i = rng.integers(n // 4, 3 * n // 4, size=3)
+            q[i[2], i[1], i[0]] = 1.0
+        else:
+            c = rng.uniform(0.3, 0.7, size=3)
+            q = gaussian_blob(dims, c, rng.uniform(0.7, 4.0) / n)
+        qs.append(_f32(q))
+    return Medium("p%d_train_%d_s%d" % (order, n, seed), order, dims, _f32(st), _f32(alb), g, sigma_t_min, qs)
+
+
 def config_p5_nebula(n=128, seed=3, g=0.0, order=5, sigma_t_min=1.0, nblobs=32):
     """P5, n^3 nebula: (sum of 32 anisotropic Gaussian blobs) * fBm, scaled to
     sigma_t in [0, 200]; albedo 0.95; emission Q^{00} = 1 in 2 seeded cells."""
