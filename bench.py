@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("pn_kernels.h", "pn_tables.h", "pn_api.hip"):
+    for f in ("pn_kernels.h", "pn_tables.h", "pn_launch.h"):
         with open(os.path.join(ROOT, "paper_1807_00410_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

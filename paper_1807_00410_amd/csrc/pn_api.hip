@@ -733,7 +733,7 @@ static pn_status ensure_net_bufs(pn_ctx* c) {
 }
 
 static int cells_grid(const NetGeom& g) {
-  const long long n = (long long)g.nx * g.ny * g.nz;
+  const long long n = (long long)g.nx * g.ny * g.nz * g.nk;
   long long b = (n + kBlock - 1) / kBlock;
   return (int)std::max(1LL, std::min(b, 1024LL));
 }

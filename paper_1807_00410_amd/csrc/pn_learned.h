@@ -4,8 +4,10 @@
 // Network grid: the cell grid rounded up to multiples of 8 (nx8 x ny8 x nz8),
 // cells beyond the medium holding zeros.  Input channels per cell:
 //   0: sigma_t h (thresholded), 1: sigma_a h = sigma_t (1 - albedo) h,
-//   2: source / max|source| (coefficient 0 of a lattice vector at the cell
-//      centres), 3..31: zero.
+//   2 + k (k < 16): coefficient k of the source (a lattice vector: the
+//      emission Q, or a residual) at the lattice point with the cell's
+//      indices, divided by the largest |value| of these over all cells;
+//   the rest zero.  An isotropic emission fills channel 2 only.
 // Output / target channel k < 16 holds coefficient k (bands l <= 3) at the
 // lattice point with the cell's indices (the cell centre for class (0,0,0),
 // its lower faces / edges / corner otherwise); the far-boundary points of
@@ -39,15 +41,18 @@ __device__ __forceinline__ long long lat(const NetGeom& g, int k, int x, int y, 
   return g.base[k] + (long long)z * g.sz[k] + (long long)y * g.sy[k] + x;
 }
 
-// max |v| over the cells of coefficient 0 of an FP32 lattice vector (float
-// bits combined with atomicMax, valid for non-negative floats; *out zeroed first).
+// max |v| over the cells and the coefficients k < nk of an FP32 lattice vector
+// (float bits combined with atomicMax, valid for non-negative floats; *out
+// zeroed first).
 static __global__ void __launch_bounds__(kBlock) k_src_absmax(const float* __restrict__ v, const NetGeom g,
                                                               unsigned* __restrict__ out) {
   float m = 0.f;
-  const long long n = (long long)g.nx * g.ny * g.nz;
+  const long long n = (long long)g.nx * g.ny * g.nz * g.nk;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
-    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
-    m = fmaxf(m, fabsf(v[lat(g, 0, x, y, z)]));
+    const int k = (int)(i % g.nk);
+    const long long c = i / g.nk;
+    const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((long long)g.nx * g.ny));
+    m = fmaxf(m, fabsf(v[lat(g, k, x, y, z)]));
   }
   for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
@@ -64,17 +69,22 @@ static __global__ void __launch_bounds__(kBlock) k_net_features(const float2* __
   const long long n = (long long)g.nx8 * g.ny8 * g.nz8;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     const int cx = (int)(i % g.nx8), cy = (int)((i / g.nx8) % g.ny8), cz = (int)(i / ((long long)g.nx8 * g.ny8));
-    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+    uint16_t f[nn::kC];
+#pragma unroll
+    for (int c = 0; c < nn::kC; ++c) f[c] = 0;
     if (cx < g.nx && cy < g.ny && cz < g.nz) {
       const float2 m = med[((long long)(cz + 1) * g.CY + (cy + 1)) * g.CX + (cx + 1)];
-      f0 = m.x * h;
-      f1 = m.x * (1.f - m.y) * h;
-      f2 = src[lat(g, 0, cx, cy, cz)] * inv;
+      f[0] = nn::f2bf(m.x * h);
+      f[1] = nn::f2bf(m.x * (1.f - m.y) * h);
+#pragma unroll
+      for (int k = 0; k < kNetOut; ++k)
+        if (k < g.nk) f[2 + k] = nn::f2bf(src[lat(g, k, cx, cy, cz)] * inv);
     }
     uint4* o = reinterpret_cast<uint4*>(x + i * nn::kC);
-    o[0] = make_uint4(nn::f2bf(f0) | ((uint32_t)nn::f2bf(f1) << 16), nn::f2bf(f2), 0u, 0u);
-    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-    o[1] = z; o[2] = z; o[3] = z;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      o[q] = make_uint4(f[8 * q] | ((uint32_t)f[8 * q + 1] << 16), f[8 * q + 2] | ((uint32_t)f[8 * q + 3] << 16),
+                        f[8 * q + 4] | ((uint32_t)f[8 * q + 5] << 16), f[8 * q + 6] | ((uint32_t)f[8 * q + 7] << 16));
   }
 }
 

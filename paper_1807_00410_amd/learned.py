@@ -91,6 +91,37 @@ def generate(n=64, nmedia=250, nrhs=8, seed0=1000, chunk=16, tol=1e-5, workers=1
     return X, T, dict(samples=N, seconds=time.time() - t0, solve_seconds=solve_s, mean_iters=float(np.mean(iters)))
 
 
+def generate_corrections(n=64, nmedia=64, nrhs=8, seed0=5000, stages=(1e-2, 1e-4), tol=1e-5, workers=12,
+                         data="p3", log=print):
+    """Correction pairs for the learned refinement step: for every system the
+    FP64 residual r_j = Q - A x_j after a partial solve to stages[j] and the
+    remaining correction x* - x_j (x* solved to tol).  Returns (X, T, stats)
+    as generate(); the residual feeds all 16 source channels."""
+    N = nmedia * nrhs * len(stages)
+    X = torch.empty((N, n, n, n, 32), dtype=torch.bfloat16, device="cuda")
+    T = torch.empty((N, n, n, n, 16), dtype=torch.bfloat16, device="cuda")
+    t0 = time.time()
+    k = 0
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        for m in ex.map(_medium, [(n, seed0 + i, nrhs, data) for i in range(nmedia)]):
+            s = Solver(m.order, m.dims, _dev(m.sigma_t), _dev(m.albedo), g=m.g, sigma_t_min=m.sigma_t_min, bc=m.bc)
+            r = torch.empty(s.n, dtype=torch.float64, device="cuda")
+            for q in m.q00:
+                b = s.rhs_from_q00(_dev(q))
+                parts = [s.solve(b, tol=st, raise_on_fail=False)[0] for st in stages]
+                xs, d = s.solve(b, x=parts[-1].clone(), tol=tol, use_guess=True)
+                for xj in parts:
+                    s.residual64(b, xj, r)
+                    X[k] = s.net_features(r.float())[0]
+                    T[k] = s.net_targets(xs - xj)[0]
+                    k += 1
+            s.close()
+            if k % (nrhs * len(stages) * 16) == 0:
+                log("  corrections: %d/%d samples, %.1f s" % (k, N, time.time() - t0))
+    torch.cuda.synchronize()
+    return X, T, dict(samples=N, seconds=time.time() - t0)
+
+
 def train(net, X, T, epochs=10, batch=4, lr=2e-3, val=16, seed=0, log=print):
     """Adam with a cosine learning-rate decay; the last `val` samples are held
     out for the validation loss.  Batches are contiguous runs of samples, in a
@@ -150,6 +181,8 @@ def main():
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval", action="store_true", help="evaluate on held-out P3 96^3 and P5 128^3 media")
+    ap.add_argument("--corrections", type=int, default=0,
+                    help="media whose partially solved residuals add (residual -> correction) samples")
     ap.add_argument("--data", choices=("p3", "mixed"), default="p3",
                     help="p3: the P3 fBm generator (sigma_t 50 fBm, blobs of std 4 cells); mixed: per-medium "
                          "extinction scale and point / narrow sources")
@@ -157,6 +190,13 @@ def main():
     log = lambda *a: print(*a, flush=True)
     log("generating %d x %d P3 %d^3 samples" % (args.media, args.nrhs, args.n))
     X, T, st = generate(n=args.n, nmedia=args.media, nrhs=args.nrhs, data=args.data, log=log)
+    if args.corrections > 0:
+        log("generating correction samples from %d media" % args.corrections)
+        Xc, Tc, _ = generate_corrections(n=args.n, nmedia=args.corrections, nrhs=args.nrhs, data=args.data, log=log)
+        # the validation tail stays a guess sample set; corrections go in front
+        X = torch.cat([Xc, X])
+        T = torch.cat([Tc, T])
+        del Xc, Tc
     net = Net(seed=1)
     log("training: %d epochs, batch %d, lr %g" % (args.epochs, args.batch, args.lr))
     train(net, X, T, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)

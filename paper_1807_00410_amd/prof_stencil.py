@@ -2,7 +2,7 @@
 128^3 nebula workload a fixed number of times, then a plain 1 GiB device copy
 whose counter readings calibrate FETCH_SIZE / WRITE_SIZE.
 
-    rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_1807_00410_amd.prof_stencil
+    rocprofv3 --pmc FETCH_SIZE -- python3 paper_1807_00410_amd/prof_stencil.py
 """
 import argparse
 import os
@@ -19,6 +19,7 @@ def main():
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--transpose", action="store_true")
+    ap.add_argument("--zchunk", type=int, default=2, help="launch z-chunk (the autotuner's choice at P5 128^3)")
     args = ap.parse_args()
     import torch
     from synth import config_p5_nebula
@@ -26,6 +27,7 @@ def main():
     m = config_p5_nebula(n=args.n, order=args.order, g=0.0)
     s = Solver(m.order, m.dims, torch.as_tensor(m.sigma_t).cuda(), torch.as_tensor(m.albedo).cuda(),
                g=m.g, sigma_t_min=m.sigma_t_min)
+    s.set_zchunk(args.zchunk)
     ms = s.bench_apply(args.iters, args.transpose)
     cells = m.dims[0] * m.dims[1] * m.dims[2]
     print("apply %.4f ms, %.1f GB/s algorithmic (%d unknowns)" % (ms, (8 * s.n + 8 * cells) / ms / 1e6, s.n),

@@ -52,8 +52,21 @@ def test_features_and_targets_definitions():
     f[:nz, :ny, :nx, 2] = q / np.abs(q).max()
     assert np.all(np.abs(x[..., :3] - f) <= 2.0 ** -7 * np.abs(f) + 1e-7)
     assert np.all(x[..., 3:] == 0.0)
-    # a solution-shaped vector: target channel k = coefficient k at the cell's lattice point / max|L00|
+    # an anisotropic source (a residual-like vector): channel 2 + k = coefficient k / max over k < 16
     lay = s.layout
+    v = np.random.default_rng(2).normal(size=s.n).astype(np.float32)
+    xa = bf16_host(s.net_features(dev(v)))[0]
+    blocks = []
+    for k in range(16):
+        ex, ey, ez = lay.ext[k]
+        blocks.append(v[lay.offset[k]:lay.offset[k + 1]].reshape(ez, ey, ex)[:nz, :ny, :nx].astype(np.float64))
+    vmax = max(np.abs(b).max() for b in blocks)
+    for k in range(16):
+        refk = np.zeros((16, 16, 16))
+        refk[:nz, :ny, :nx] = blocks[k] / vmax
+        assert np.all(np.abs(xa[..., 2 + k] - refk) <= 2.0 ** -8 * np.abs(refk) + 1e-7)
+    assert np.all(xa[..., 18:] == 0.0)
+    # a solution-shaped vector: target channel k = coefficient k at the cell's lattice point / max|L00|
     u = np.random.default_rng(1).normal(size=s.n)
     t = bf16_host(s.net_targets(dev(u, torch.float64)))[0]
     rms = np.abs(u[:lay.offset[1]]).max()
