@@ -27,8 +27,9 @@ namespace {
 
 struct Group {
   int order = 0, per = 0;
-  int2* work = nullptr;
+  int2* work = nullptr;         // device list of the systems in the current launch set
   int nwork = 0;
+  std::vector<int2> full;       // every (system, tile) of the group
 };
 
 }  // namespace
@@ -52,6 +53,8 @@ struct pn_batch {
   std::vector<Group> groups;
   int2* vwork = nullptr;
   int nvwork = 0;
+  std::vector<int2> vfull;        // every (system, chunk)
+  int nlaunch = 0;                // systems in the current launch set
   hipGraphExec_t gexec = nullptr;
   int giters = 0;
   long long unknowns = 0;
@@ -125,6 +128,7 @@ BatchLaunch roles(const pn_batch* b, int ix, int ix2, int iy, int iy2, double ts
 
 hipError_t stencil_all(const pn_batch* b, int kind, const BatchLaunch& bl, hipStream_t s) {
   for (const Group& g : b->groups) {
+    if (g.nwork == 0) continue;
     hipError_t e = launch_group(g, kind, bl, s);
     if (e != hipSuccess) return e;
   }
@@ -133,6 +137,7 @@ hipError_t stencil_all(const pn_batch* b, int kind, const BatchLaunch& bl, hipSt
 
 template <int OP>
 hipError_t vec_all(const pn_batch* b, hipStream_t s) {
+  if (b->nvwork == 0) return hipSuccess;
   hipLaunchKernelGGL((k_vec_batch<OP>), dim3(b->nvwork), dim3(kBlock), 0, s, (const SysArgs*)b->sys,
                      (const int2*)b->vwork, b->nvwork);
   return hipGetLastError();
@@ -152,6 +157,33 @@ hipError_t enqueue_batch_iteration(const pn_batch* b, int rin, int rout, hipStre
   if (e == hipSuccess) e = fin_all<BF_BETA>(b, s);
   if (e == hipSuccess) e = vec_all<BO_UPDATE_XP>(b, s);
   return e;
+}
+
+// Restricts every launch to the systems with keep[i] != 0 (a subset of the
+// full work lists, same order) and drops the captured graph.  Blocks of
+// finished systems would otherwise still be dispatched, only to return.
+pn_status compact(pn_batch* b, const std::vector<char>& keep, hipStream_t s) {
+  int n = 0;
+  for (char k : keep) n += k ? 1 : 0;
+  if (n == b->nlaunch) return PN_OK;
+  std::vector<int2> tmp;
+  for (Group& g : b->groups) {
+    tmp.clear();
+    for (const int2& w : g.full)
+      if (keep[w.x]) tmp.push_back(w);
+    g.nwork = (int)tmp.size();
+    if (g.nwork) B_HIP(hipMemcpyAsync(g.work, tmp.data(), sizeof(int2) * tmp.size(), hipMemcpyHostToDevice, s));
+    B_HIP(hipStreamSynchronize(s));  // tmp is reused
+  }
+  tmp.clear();
+  for (const int2& w : b->vfull)
+    if (keep[w.x]) tmp.push_back(w);
+  b->nvwork = (int)tmp.size();
+  if (b->nvwork) B_HIP(hipMemcpyAsync(b->vwork, tmp.data(), sizeof(int2) * tmp.size(), hipMemcpyHostToDevice, s));
+  B_HIP(hipStreamSynchronize(s));
+  b->nlaunch = n;
+  if (b->gexec) { hipGraphExecDestroy(b->gexec); b->gexec = nullptr; b->giters = 0; }
+  return PN_OK;
 }
 
 pn_status build_batch_graph(pn_batch* b, int iters) {
@@ -300,8 +332,9 @@ extern "C" pn_status pn_batch_setup(int nprob, const pn_problem* probs, int nrhs
     g.per = kv.first.second;
     g.nwork = (int)kv.second.size();
     SETUP_B(hipMalloc(&g.work, sizeof(int2) * g.nwork));
-    b->groups.push_back(g);
     SETUP_B(hipMemcpy(g.work, kv.second.data(), sizeof(int2) * g.nwork, hipMemcpyHostToDevice));
+    g.full = std::move(kv.second);
+    b->groups.push_back(std::move(g));
   }
   // vector work list: (system, chunk)
   {
@@ -314,7 +347,9 @@ extern "C" pn_status pn_batch_setup(int nprob, const pn_problem* probs, int nrhs
     b->nvwork = (int)vw.size();
     SETUP_B(hipMalloc(&b->vwork, sizeof(int2) * b->nvwork));
     SETUP_B(hipMemcpy(b->vwork, vw.data(), sizeof(int2) * b->nvwork, hipMemcpyHostToDevice));
+    b->vfull = std::move(vw);
   }
+  b->nlaunch = b->nsys;
   SETUP_B(hipMalloc(&b->active, sizeof(int)));
   SETUP_B(hipHostMalloc(&b->active_host, sizeof(int), hipHostMallocDefault));
   SETUP_B(hipMalloc(&b->flag, sizeof(int)));
@@ -408,8 +443,10 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
     }
   }
   const int gi = o.graph_iters < 2 ? 2 : (o.graph_iters + 1) & ~1;  // even: r ends in r0
-  pn_status gs = build_batch_graph(b, gi);
-  if (gs != PN_OK) return gs;
+  {
+    pn_status cs = compact(b, std::vector<char>(b->nsys, 1), ss);
+    if (cs != PN_OK) return cs;
+  }
   DevState init;
   std::memset(&init, 0, sizeof(init));
   init.max_iters = o.max_iter;
@@ -458,20 +495,45 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
     }
     if (nactive == 0) break;
     B_HIP(hipMemcpyAsync(b->st, b->st_host, sizeof(DevState) * b->nsys, hipMemcpyHostToDevice, ss));
+    std::vector<char> keep(b->nsys);
+    for (int i = 0; i < b->nsys; ++i) keep[i] = b->st_host[i].frozen ? 0 : 1;
+    pn_status cs = compact(b, keep, ss);
+    if (cs != PN_OK) return cs;
     // inner solves  A d = r0  from d = 0
     B_HIP(vec_all<BO_ZERO_D>(b, ss));
     B_HIP(stencil_all(b, K_F32_APPLY, roles(b, BV_R0, -1, BV_S, -1, -1.0, 0), ss));
     B_HIP(fin_all<BF_INIT>(b, ss));
     B_HIP(vec_all<BO_COPY_SP>(b, ss));
     for (;;) {
+      if (!b->gexec) {
+        pn_status e = build_batch_graph(b, gi);
+        if (e != PN_OK) return e;
+      }
       B_HIP(hipGraphLaunch(b->gexec, ss));
       hipLaunchKernelGGL(k_batch_active, dim3(1), dim3(kBlock), 0, ss, (const SysArgs*)b->sys, b->nsys, b->active);
       B_HIP(hipGetLastError());
       B_HIP(hipMemcpyAsync(b->active_host, b->active, sizeof(int), hipMemcpyDeviceToHost, ss));
       B_HIP(hipStreamSynchronize(ss));
-      if (*b->active_host == 0) break;
+      const int act = *b->active_host;
+      if (act == 0) break;
+      if (2 * act <= b->nlaunch) {  // half the launch set finished: launch only the running systems
+        B_HIP(hipMemcpyAsync(b->st_host, b->st, sizeof(DevState) * b->nsys, hipMemcpyDeviceToHost, ss));
+        B_HIP(hipStreamSynchronize(ss));
+        std::vector<char> run(b->nsys);
+        for (int i = 0; i < b->nsys; ++i) run[i] = (!b->st_host[i].frozen && !b->st_host[i].done) ? 1 : 0;
+        pn_status cs = compact(b, run, ss);
+        if (cs != PN_OK) return cs;
+      }
+    }
+    {  // x += d for every system of this refinement step
+      pn_status cs = compact(b, keep, ss);
+      if (cs != PN_OK) return cs;
     }
     B_HIP(vec_all<BO_AXPY64>(b, ss));
+  }
+  {
+    pn_status cs = compact(b, std::vector<char>(b->nsys, 1), ss);
+    if (cs != PN_OK) return cs;
   }
   // padded -> packed (also after a failed solve: x is the last iterate)
   for (int i = 0; i < b->nsys; ++i)
