@@ -226,7 +226,7 @@ def main():
     fp32_single = None
     if not args.no_fp64:
         xx = torch.zeros_like(x)
-        _, i32 = s.solve(rhs, x=xx, tol=args.tol, inner_tol=1e-9, max_refine=1, max_iter=8000,
+        _, i32 = s.solve(rhs, x=xx, tol=args.tol, inner_tol=1e-9, max_refine=1, max_iter=8000, variant="cgls",
                          raise_on_fail=False)
         fp32_single = {"seconds": i32["seconds"], "iters": i32["inner_iters"], "rel_residual": i32["rel_residual"],
                        "status": i32["status"]}
@@ -278,7 +278,7 @@ def main():
         "config": {"workload": "P%d nebula %d^3 (32 Gaussian blobs x fBm, sigma_t in [0,200], albedo 0.95, "
                                "g=%g, 2 point sources), vacuum boundary, tol %g"
                                % (m.order, args.n, m.g, args.tol),
-                   "unknowns": s.n, "solver": "FP32 CGLS + FP64 dots/refinement (plain)",
+                   "unknowns": s.n, "solver": "FP32 CG on the normal equations + FP64 dots/refinement (plain)",
                    "inner_tol": args.inner_tol, "zchunk": zchunk},
         "iters": infos[-1]["inner_iters"],
         "outer_iters": infos[-1]["outer_iters"],

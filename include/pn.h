@@ -98,7 +98,7 @@ typedef struct {
   double inner_tol;   /* relative reduction of the inner FP32 residual         */
   int use_guess;      /* 0: start from x = 0; 1: start from the x passed in    */
   int graph_iters;    /* Krylov iterations per captured HIP graph launch       */
-  int variant;        /* PN_VARIANT_AUTO or PN_VARIANT_CGLS (see pn_solve)     */
+  int variant;        /* PN_VARIANT_AUTO, _CGLS or _CG (see below)             */
   int learned;        /* PN_LEARNED_* (needs a network, pn_attach_net in pn_nn.h) */
 } pn_solve_opts;
 
@@ -116,11 +116,13 @@ typedef struct {
 #define PN_LEARNED_GUESS 1
 #define PN_LEARNED_GUESS_CORRECT 2
 
-/* Krylov variant of the FP32 inner solve.  AUTO and CGLS: the residual-based
- * CGLS form (r <- r - alpha q fused into s = A^T r).  CG: CG on the normal
+/* Krylov variant of the FP32 inner solve.  CGLS: the residual-based CGLS
+ * form (r <- r - alpha q fused into s = A^T r).  AUTO and CG: CG on the normal
  * equations A^T A u = A^T Q with the recursive normal residual
  * (s <- s - alpha A^T q, ||r||^2 <- ||r||^2 - alpha gamma; 10 vector passes
- * per iteration); needs the LDS-tiled stencil (pn_set_tiles), else CGLS. */
+ * per iteration, and the A^T pass streams one vector instead of two), on
+ * whichever stencil is in use.  The FP64 refinement checks the true residual
+ * either way. */
 #define PN_VARIANT_AUTO 0
 #define PN_VARIANT_CGLS 1
 #define PN_VARIANT_CG 2
@@ -181,10 +183,10 @@ pn_status pn_residual64(pn_ctx* ctx, const float* rhs, const double* x,
 
 /* Solves A x = Q (rhs = Q, device FP32; x device FP64, in/out) to
  * ||Q - A x||_2 <= tol ||Q||_2 with the residual evaluated in FP64.
- * PN_FP32_IR: iterative refinement around CGLS (conjugate gradients on the
- * normal equations without forming A^T A, section "Runtime" / "Results") run
- * in FP32 with FP64 dot products and scalars.  PN_FP64: CGLS in FP64
- * throughout.  Returns PN_ERR_NOT_CONVERGED (x = last iterate, finite) when
+ * PN_FP32_IR: iterative refinement around conjugate gradients on the normal
+ * equations without forming A^T A (section "Runtime" / "Results"; variant CG
+ * by default, CGLS on request) run in FP32 with FP64 dot products and
+ * scalars.  PN_FP64: CGLS in FP64 throughout.  Returns PN_ERR_NOT_CONVERGED (x = last iterate, finite) when
  * the limits are hit, PN_ERR_NONFINITE for a non-finite rhs.  rhs == 0
  * returns x = 0 immediately.  opts NULL = defaults; info may be NULL. */
 pn_status pn_solve(pn_ctx* ctx, const float* rhs, double* x, double tol,

@@ -99,9 +99,11 @@ pn_status pn_net_set_stream(pn_net* net, void* stream);
  * of 8 (the extra cells carry zero features). */
 pn_status pn_net_grid(const pn_ctx* ctx, int* nx8, int* ny8, int* nz8);
 /* Network input for the context's medium and a source (device FP32 vector in
- * the context's packed layout; its coefficient 0 at the cell centres is the
- * source): x [nz8][ny8][nx8][32] bfloat16 with channels sigma_t h
- * (thresholded), sigma_a h, source / max|source|, then zeros.  On the
+ * the context's packed layout: the emission Q, or a residual):
+ * x [nz8][ny8][nx8][32] bfloat16 with channels sigma_t h (thresholded),
+ * sigma_a h, then for k < min(16, coefficients) the source's coefficient k at
+ * the lattice point with the cell's indices divided by the largest such
+ * |value|, then zeros (an isotropic emission fills channel 2 only).  On the
  * context's stream. */
 pn_status pn_net_features(pn_ctx* ctx, const float* src, uint16_t* x);
 /* Training target for a solution (device FP64 vector, packed layout):

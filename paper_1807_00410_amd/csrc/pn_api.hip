@@ -288,6 +288,7 @@ extern "C" pn_status pn_autotune(pn_ctx* c, int iters, int* zchunk, double* ms) 
   tune_store(c, z, bms);
   if (c->gexec32) { hipGraphExecDestroy(c->gexec32); c->gexec32 = nullptr; c->giters32 = 0; }
   if (c->gexec64) { hipGraphExecDestroy(c->gexec64); c->gexec64 = nullptr; c->giters64 = 0; }
+  if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
   if (zchunk) *zchunk = z;
   if (ms) *ms = bms;
   return PN_OK;
@@ -476,6 +477,7 @@ extern "C" pn_status pn_set_zchunk(pn_ctx* c, int zchunk) {
   if (c->nblocks > c->max_blocks) { set_geometry(c, 0); return fail(c, PN_ERR_ARG, "too many blocks"); }
   if (c->gexec32) { hipGraphExecDestroy(c->gexec32); c->gexec32 = nullptr; c->giters32 = 0; }
   if (c->gexec64) { hipGraphExecDestroy(c->gexec64); c->gexec64 = nullptr; c->giters64 = 0; }
+  if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
   return PN_OK;
 }
 
@@ -634,20 +636,22 @@ static hipError_t enqueue_iteration(pn_ctx* c, T* d, T* p, T* q, T* s, const T* 
   return hipGetLastError();
 }
 
-// One iteration of CG on the normal equations (FP32 vectors, LDS-tiled stencil):
+// One iteration of CG on the normal equations (FP32 vectors; LDS-tiled or
+// register-window stencil):
 // q = A p | alpha | s -= alpha A^T q | beta | x += alpha p, p = s + beta p.
 static hipError_t enqueue_iteration_cg(pn_ctx* c, float* d, float* p, float* q, float* s, hipStream_t st) {
   StencilArgs a = base_args(c);
   a.st = c->st;
   a.partials = c->partials;
   a.x = p; a.y = q; a.tsign = 1.0;
-  hipError_t e = launch_lds(c, M_APPLY, true, a, st);
+  const int nb = c->use_lds ? c->lnblocks : c->nblocks;
+  hipError_t e = c->use_lds ? launch_lds(c, M_APPLY, true, a, st) : launch_stencil<float, M_APPLY, float>(c, a, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fin_alpha_cg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->lnblocks);
+  hipLaunchKernelGGL(k_fin_alpha_cg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, nb);
   a.x = q; a.y = s; a.tsign = -1.0;
-  e = launch_lds(c, M_SUPD, true, a, st);
+  e = c->use_lds ? launch_lds(c, M_SUPD, true, a, st) : launch_stencil<float, M_SUPD, float>(c, a, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fin_beta_cg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->lnblocks);
+  hipLaunchKernelGGL(k_fin_beta_cg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, nb);
   hipLaunchKernelGGL((k_update_xp<float>), dim3(grid_for(c->nv / 4 + 1)), dim3(kBlock), 0, st, d, p,
                      (const float*)s, (long)c->nv, (const DevState*)c->st);
   return hipGetLastError();
@@ -851,10 +855,11 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     r0 = c->r64[0]; r1 = c->r64[1]; s = c->s64; p = c->p64; q = c->q64; d = c->d64;
     gexec = &c->gexec64; giters = &c->giters64;
   }
-  // FP32 with the LDS-tiled stencil: CG on the normal equations with the
-  // recursive normal residual (10 vector passes per iteration); otherwise
-  // CGLS with the recursive residual r (11 passes, r ping-pong).
-  const bool cg = (sizeof(T) == 4) && c->use_lds && o.variant == PN_VARIANT_CG;
+  // FP32, variant CG: CG on the normal equations with the recursive normal
+  // residual (10 vector passes per iteration, the A^T pass streams one
+  // vector); otherwise CGLS with the recursive residual r (11 passes, r
+  // ping-pong, the A^T pass streams two).
+  const bool cg = (sizeof(T) == 4) && o.variant != PN_VARIANT_CGLS;
   if (cg) {
     gexec = &c->gexec_cg;
     giters = &c->giters_cg;
@@ -942,10 +947,10 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, d, (long)c->nv, T(0));
     StencilArgs a = base_args(c);
     a.x = r0; a.y = s; a.tsign = -1.0; a.partials = c->partials;
-    if (cg) PN_HIP(launch_lds(c, M_APPLY, true, a, ss));
+    if (cg && c->use_lds) PN_HIP(launch_lds(c, M_APPLY, true, a, ss));
     else PN_HIP((launch_stencil<T, M_APPLY, T>(c, a, ss)));
     hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials,
-                       cg ? c->lnblocks : c->nblocks, itol * itol);
+                       (cg && c->use_lds) ? c->lnblocks : c->nblocks, itol * itol);
     PN_HIP(hipGetLastError());
     PN_HIP(hipMemcpyAsync(p, s, sizeof(T) * c->nv, hipMemcpyDeviceToDevice, ss));  // p = s
     for (;;) {

@@ -57,6 +57,7 @@ struct pn_batch {
   int nlaunch = 0;                // systems in the current launch set
   hipGraphExec_t gexec = nullptr;
   int giters = 0;
+  bool gcg = false;
   long long unknowns = 0;
   std::string err;
 };
@@ -149,12 +150,20 @@ hipError_t fin_all(const pn_batch* b, hipStream_t s) {
   return hipGetLastError();
 }
 
-// One CGLS iteration of every running system (r ping-pong rin -> rout).
-hipError_t enqueue_batch_iteration(const pn_batch* b, int rin, int rout, hipStream_t s) {
+// One Krylov iteration of every running system, as pn_solve's FP32 inner
+// solve: CG on the normal equations (s -= alpha A^T q), or CGLS (r ping-pong
+// rin -> rout, r' = r - alpha q fused into s = A^T r').
+hipError_t enqueue_batch_iteration(const pn_batch* b, bool cg, int rin, int rout, hipStream_t s) {
   hipError_t e = stencil_all(b, K_F32_APPLY, roles(b, BV_P, -1, BV_Q, -1, 1.0, 1), s);
-  if (e == hipSuccess) e = fin_all<BF_ALPHA>(b, s);
-  if (e == hipSuccess) e = stencil_all(b, K_F32_TRANSR, roles(b, rin, BV_Q, BV_S, rout, -1.0, 1), s);
-  if (e == hipSuccess) e = fin_all<BF_BETA>(b, s);
+  if (cg) {
+    if (e == hipSuccess) e = fin_all<BF_ALPHA_CG>(b, s);
+    if (e == hipSuccess) e = stencil_all(b, K_F32_SUPD, roles(b, BV_Q, -1, BV_S, -1, -1.0, 1), s);
+    if (e == hipSuccess) e = fin_all<BF_BETA_CG>(b, s);
+  } else {
+    if (e == hipSuccess) e = fin_all<BF_ALPHA>(b, s);
+    if (e == hipSuccess) e = stencil_all(b, K_F32_TRANSR, roles(b, rin, BV_Q, BV_S, rout, -1.0, 1), s);
+    if (e == hipSuccess) e = fin_all<BF_BETA>(b, s);
+  }
   if (e == hipSuccess) e = vec_all<BO_UPDATE_XP>(b, s);
   return e;
 }
@@ -186,15 +195,15 @@ pn_status compact(pn_batch* b, const std::vector<char>& keep, hipStream_t s) {
   return PN_OK;
 }
 
-pn_status build_batch_graph(pn_batch* b, int iters) {
-  if (b->gexec && b->giters == iters) return PN_OK;
+pn_status build_batch_graph(pn_batch* b, int iters, bool cg) {
+  if (b->gexec && b->giters == iters && b->gcg == cg) return PN_OK;
   if (b->gexec) { hipGraphExecDestroy(b->gexec); b->gexec = nullptr; b->giters = 0; }
   hipGraph_t g = nullptr;
   B_HIP(hipStreamBeginCapture(b->sstream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
   for (int i = 0; i < iters && e == hipSuccess; ++i)
-    e = (i & 1) ? enqueue_batch_iteration(b, BV_R1, BV_R0, b->sstream)
-                : enqueue_batch_iteration(b, BV_R0, BV_R1, b->sstream);
+    e = (i & 1) ? enqueue_batch_iteration(b, cg, BV_R1, BV_R0, b->sstream)
+                : enqueue_batch_iteration(b, cg, BV_R0, BV_R1, b->sstream);
   hipError_t e2 = hipStreamEndCapture(b->sstream, &g);
   if (e != hipSuccess) {
     if (g) hipGraphDestroy(g);
@@ -205,6 +214,7 @@ pn_status build_batch_graph(pn_batch* b, int iters) {
   hipGraphDestroy(g);
   if (e3 != hipSuccess) return bfail(b, PN_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e3));
   b->giters = iters;
+  b->gcg = cg;
   return PN_OK;
 }
 
@@ -506,7 +516,7 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
     B_HIP(vec_all<BO_COPY_SP>(b, ss));
     for (;;) {
       if (!b->gexec) {
-        pn_status e = build_batch_graph(b, gi);
+        pn_status e = build_batch_graph(b, gi, o.variant != PN_VARIANT_CGLS);
         if (e != PN_OK) return e;
       }
       B_HIP(hipGraphLaunch(b->gexec, ss));

@@ -157,7 +157,7 @@ inline hipError_t launch_stencil(const pn_ctx* c, const StencilArgs& a, hipStrea
   const bool per = c->bc == PN_BC_PERIODIC;
   const bool norm = !(MODE == M_APPLY && a.partials == nullptr);
   int kind;
-  if constexpr (sizeof(T) == 4) kind = (MODE == M_APPLY) ? K_F32_APPLY : K_F32_TRANSR;
+  if constexpr (sizeof(T) == 4) kind = (MODE == M_APPLY) ? K_F32_APPLY : (MODE == M_SUPD ? K_F32_SUPD : K_F32_TRANSR);
   else if constexpr (MODE == M_APPLY) kind = K_F64_APPLY;
   else if constexpr (MODE == M_TRANSR) kind = K_F64_TRANSR;
   else kind = (sizeof(TO) == 4) ? K_F64_RESID32 : K_F64_RESID64;

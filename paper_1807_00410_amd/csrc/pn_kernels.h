@@ -160,6 +160,7 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 //   M_APPLY  y = op(x)                         [||y||^2]
 //   M_TRANSR r' = r - alpha q, y = A^T r'      [writes r' to y2; ||y||^2, ||r'||^2]
 //   M_RESID  y = Q - A x                       [||y||^2, ||Q||^2]
+//   M_SUPD   y = y - alpha op(x)               [||y||^2]
 template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
 __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) {
   using TB = Table<N>;
@@ -178,7 +179,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
   TO* __restrict__ Y = static_cast<TO*>(a.y);
   TO* __restrict__ Y2 = static_cast<TO*>(a.y2);
   T alpha = T(0);
-  if constexpr (MODE == M_TRANSR) alpha = T(a.st->alpha);
+  if constexpr (MODE == M_TRANSR || MODE == M_SUPD) alpha = T(a.st->alpha);
   const T tinvh = T(a.tsign * a.invh);
   const long long cs = a.cs;
 
@@ -345,6 +346,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
                   out = q - out;
                   cn1 = fmadd<T>(q, q, cn1);
                 }
+                if constexpr (MODE == M_SUPD) out = fmadd<T>(-alpha, out, T(ldb(Y + base, oo)));
                 stb(Y + base, oo, TO(out));
                 if constexpr (NORM) cn0 = fmadd<T>(out, out, cn0);
                 if constexpr (MODE == M_TRANSR) {
@@ -675,7 +677,7 @@ static __global__ void __launch_bounds__(kBlock) k_check_finite(const float* __r
 
 // ------------------------------------------------------- batch (scalars) --
 // One block per system; a finished (frozen) system is skipped.
-enum BatchFin { BF_ALPHA = 0, BF_BETA = 1, BF_INIT = 2, BF_RESID = 3 };
+enum BatchFin { BF_ALPHA = 0, BF_BETA = 1, BF_INIT = 2, BF_RESID = 3, BF_ALPHA_CG = 4, BF_BETA_CG = 5 };
 
 template <int WHICH>
 __global__ void __launch_bounds__(kBlock) k_fin_batch(const SysArgs* __restrict__ sys) {
@@ -687,6 +689,8 @@ __global__ void __launch_bounds__(kBlock) k_fin_batch(const SysArgs* __restrict_
   if constexpr (WHICH == BF_ALPHA) fin_alpha(st, p, n);
   else if constexpr (WHICH == BF_BETA) fin_beta(st, p, n);
   else if constexpr (WHICH == BF_INIT) fin_init(st, p, n, st->itol2);
+  else if constexpr (WHICH == BF_ALPHA_CG) fin_alpha_cg(st, p, n);
+  else if constexpr (WHICH == BF_BETA_CG) fin_beta_cg(st, p, n);
   else fin_resid(st, p, n);
 }
 

@@ -14,7 +14,8 @@ enum Kind {
   K_F64_APPLY = 2,   // double -> double
   K_F64_TRANSR = 3,  // double -> double
   K_F64_RESID32 = 4, // double x, float Q -> float r = Q - A x
-  K_F64_RESID64 = 5  // double x, float Q -> double r
+  K_F64_RESID64 = 5, // double x, float Q -> double r
+  K_F32_SUPD = 6     // float: s = s - alpha op(x) (CG on the normal equations)
 };
 
 template <int N, typename T, int MODE, typename TO>
@@ -39,6 +40,7 @@ hipError_t launch_order(int kind, bool per, bool norm, const StencilArgs& a, hip
     case K_F64_TRANSR: return launch_flavour<N, double, M_TRANSR, double>(per, true, a, s);
     case K_F64_RESID32: return launch_flavour<N, double, M_RESID, float>(per, true, a, s);
     case K_F64_RESID64: return launch_flavour<N, double, M_RESID, double>(per, true, a, s);
+    case K_F32_SUPD: return launch_flavour<N, float, M_SUPD, float>(per, true, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -58,6 +60,7 @@ hipError_t launch_batch_order(int kind, bool per, const BatchLaunch& bl, hipStre
   switch (kind) {
     case K_F32_APPLY: return launch_batch_flavour<N, float, M_APPLY, float>(per, bl, s);
     case K_F32_TRANSR: return launch_batch_flavour<N, float, M_TRANSR, float>(per, bl, s);
+    case K_F32_SUPD: return launch_batch_flavour<N, float, M_SUPD, float>(per, bl, s);
     case K_F64_RESID32: return launch_batch_flavour<N, double, M_RESID, float>(per, bl, s);
     default: return hipErrorInvalidValue;
   }

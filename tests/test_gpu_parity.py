@@ -285,3 +285,11 @@ def test_full_size_p5_apply_sampled_rows():
     bound = 16 * EPS32 * rows_of(*args, x.astype(np.float64), rows, absolute=True)
     assert np.all(np.abs(y[rows] - ref) <= bound)
     s.close()
+
+
+@pytest.mark.parametrize("order,n", [(3, 16), (5, 12), (1, 20)])
+def test_solve_cg_normal_equations_variant(order, n):
+    # CG on the normal equations with the recursive normal residual
+    # (s -= alpha A^T q in the register-window stencil): same answer to 1e-5
+    m = config_p3_fbm(n=n, seed=13, order=order)
+    _solve_and_check(m, 1e-8, "fp32_ir", variant="cg")
