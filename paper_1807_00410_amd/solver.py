@@ -287,7 +287,7 @@ class Batch:
         return ms.value
 
     def solve(self, rhs, x=None, tol=1e-8, max_iter=200000, max_refine=40, inner_tol=1e-2, use_guess=False,
-              graph_iters=32, raise_on_fail=True):
+              graph_iters=32, variant="auto", raise_on_fail=True):
         """rhs: list over systems (problem-major, nrhs per problem) of device
         FP32 vectors in the problem's packed layout.  Returns (x list, info list)."""
         ns = self.nprob * self.nrhs
@@ -298,7 +298,7 @@ class Batch:
                  for i in range(ns)]
         rp = (C.c_void_p * ns)(*[_ptr(r, torch.float32).value for r in rhs])
         xp = (C.c_void_p * ns)(*[_ptr(v, torch.float64).value for v in x])
-        opts = _opts(self.lib, "fp32_ir", max_iter, max_refine, inner_tol, use_guess, graph_iters, "auto")
+        opts = _opts(self.lib, "fp32_ir", max_iter, max_refine, inner_tol, use_guess, graph_iters, variant)
         info = (L.PnSolveInfo * ns)()
         rc = self.lib.pn_batch_solve(self.b, rp, xp, float(tol), C.byref(opts), info)
         infos = [_info(info[i].status, info[i]) for i in range(ns)]

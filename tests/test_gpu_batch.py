@@ -157,3 +157,18 @@ def test_autotune_and_cache():
         xs, infos = B.solve(rhs, tol=1e-8)
         assert all(d["status"] == 0 for d in infos)
     tune_cache_clear()
+
+
+def test_batch_cgls_variant_matches_single():
+    # the residual-based CGLS form in the batch equals pn_solve's CGLS bitwise
+    from paper_1807_00410_amd.solver import Batch
+    media = [config_small(5, (7, 6, 8), seed=8, nrhs=2), config_small(3, (9, 7, 6), seed=9, nrhs=2)]
+    with Batch(problems(media), 2) as B:
+        rhs = [packed_rhs(B.layouts[p], q) for p, m in enumerate(media) for q in m.q00]
+        xs, infos = B.solve(rhs, tol=1e-8, variant="cgls")
+    for p, m in enumerate(media):
+        for r in range(2):
+            i = p * 2 + r
+            x1, info1, _ = single_solve(m, rhs[i], tol=1e-8, variant="cgls")
+            assert infos[i]["status"] == 0 and info1["inner_iters"] == infos[i]["inner_iters"]
+            assert torch.equal(x1, xs[i])
