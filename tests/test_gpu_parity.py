@@ -293,3 +293,37 @@ def test_solve_cg_normal_equations_variant(order, n):
     # (s -= alpha A^T q in the register-window stencil): same answer to 1e-5
     m = config_p3_fbm(n=n, seed=13, order=order)
     _solve_and_check(m, 1e-8, "fp32_ir", variant="cg")
+
+
+@pytest.mark.parametrize("order,dims,tiles", [(3, (21, 18, 15), (32, 4)), (5, (17, 19, 13), (32, 4)),
+                                              (1, (33, 9, 7), (64, 4)), (7, (9, 8, 7), (16, 3))])
+def test_lds_tiled_stencil_apply_and_solve(order, dims, tiles):
+    # the opt-in LDS-tiled stencil: apply within the FP32 bound of the oracle,
+    # and the CG solve on it reaches the oracle's answer
+    print("case lds order=%d dims=%s tiles=%s" % (order, dims, tiles), flush=True)
+    from paper_1807_00410_amd.solver import PnError
+    m = config_small(order, dims, seed=order + 40)
+    A, lay = oracle_matrix(m)
+    s = make_solver(m)
+    s.set_tiles(*tiles)
+    assert s.tiles()[:2] == tiles
+    x = np.random.default_rng(order).normal(size=lay.n).astype(np.float32)
+    Mag = magnitude_matrix(m)
+    for transpose in (False, True):
+        y = s.apply(dev(x), transpose=transpose).cpu().numpy().astype(np.float64)
+        M = A.T.tocsr() if transpose else A
+        ref = M @ x.astype(np.float64)
+        bound = 16 * EPS32 * ((Mag.T.tocsr() if transpose else Mag) @ np.abs(x.astype(np.float64))) + 1e-30
+        assert np.all(np.abs(y - ref) <= bound)
+    b = rhs_isotropic(lay, m.q00[0])
+    u = oracle_solution(A, b)
+    xs, info = s.solve(s.rhs_from_q00(dev(m.q00[0])), tol=1e-8, variant="cg")
+    xs = xs.cpu().numpy()
+    assert info["status"] == 0
+    assert np.linalg.norm(b - A @ xs) / np.linalg.norm(b) <= 1.01e-8
+    assert np.linalg.norm(xs - u) / np.linalg.norm(u) <= 1e-5
+    with pytest.raises(PnError):
+        s.set_tiles(300, 300)
+    s.set_tiles(0, 0)
+    assert s.tiles()[:2] == (0, 0)
+    s.close()
