@@ -253,6 +253,44 @@ def test_periodic_fourier_mode(order):
         np.testing.assert_allclose(lay.view(u, k), want, atol=1e-12)
 
 
+@pytest.mark.parametrize("order", [1, 3])
+def test_second_order_convergence_to_the_continuous_solution(order):
+    # The continuous P_N system for a periodic homogeneous medium and a single
+    # Fourier-mode source has the exact solution Re(u e^{i kappa.x}) with
+    # (sum_d i kappa_d A_d + diag(sigma_t - g^l sigma_s)) u = e_0 (derivatives
+    # of the continuous equations, not the staggered differences).  The
+    # discrete solution sampled at each coefficient's staggered positions must
+    # approach it at second order in h ("Precomputation": central differences
+    # on the staggered grid).
+    st, alb, g = 4.0, 0.7, float(np.float32(0.3))
+    st32, alb32 = np.float32(st), np.float32(alb)
+    T = transport_couplings(order)
+    errs = []
+    for n in (8, 16, 32):
+        # kappa_z = 0: the solution is z-invariant, two periodic cells in z carry it exactly
+        dims = (n, n, 2)
+        h = 1.0 / n
+        kappa = 2 * pi * np.array([1.0, 1.0, 0.0])
+        shp = (2, n, n)
+        A, lay = assemble(order, dims, np.full(shp, st32), np.full(shp, alb32), g, 0.0, bc=1)
+        z, y, x = np.meshgrid(*[(np.arange(m) + 0.5) * h for m in dims[::-1]], indexing="ij")
+        u = direct(A, rhs_isotropic(lay, np.cos(kappa[0] * x + kappa[1] * y + kappa[2] * z)))
+        M = sum(1j * kappa[d] * T[d] for d in range(3))
+        ssv = float(st32) * float(alb32)
+        M = M + np.diag([float(st32) - ssv * g ** sh.coeff_lm(k)[0] for k in range(lay.ncoeff)])
+        e0 = np.zeros(lay.ncoeff, dtype=complex)
+        e0[0] = 1.0
+        uc = np.linalg.solve(M, e0)
+        err = 0.0
+        for k in range(lay.ncoeff):
+            px, py, pz = lay.positions(k)
+            want = np.real(uc[k] * np.exp(1j * (kappa[0] * px * h + kappa[1] * py * h + kappa[2] * pz * h)))
+            err = max(err, float(np.abs(lay.view(u, k) - want).max()))
+        errs.append(err)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.6 and 3.7 < r2 < 4.3, (errs, r1, r2)
+
+
 def test_periodic_heterogeneous_balance():
     m = config_small(3, (5, 4, 3), seed=2, bc=1)
     A, lay = assemble(3, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min, bc=1)
