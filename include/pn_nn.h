@@ -93,6 +93,7 @@ pn_status pn_net_train_step(pn_net* net, int B, int nx, int ny, int nz, const ui
 
 /* Stream of the network's launches (NULL: the null stream). */
 pn_status pn_net_set_stream(pn_net* net, void* stream);
+void* pn_net_get_stream(const pn_net* net);
 
 /* ------------------------------------------------- solver connection -- */
 /* Network grid of a solver context: the cell grid rounded up to multiples
@@ -112,7 +113,8 @@ pn_status pn_net_features(pn_ctx* ctx, const float* src, uint16_t* x);
  * over the cells; zero where there is none.  On the context's stream. */
 pn_status pn_net_targets(pn_ctx* ctx, const double* solution, uint16_t* t);
 /* Attaches a network to a solver context (NULL detaches); pn_solve uses it
- * as opts->learned asks.  The network must outlive the attachment. */
+ * as opts->learned asks, on the solver's stream (the network's own stream is
+ * restored afterwards).  The network must outlive the attachment. */
 pn_status pn_attach_net(pn_ctx* ctx, pn_net* net);
 
 #ifdef __cplusplus

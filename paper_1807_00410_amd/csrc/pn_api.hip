@@ -764,8 +764,10 @@ static pn_status net_predict(pn_ctx* c, const float* src_pad, hipStream_t s) {
   const NetGeom g = net_geom(c, true);
   pn_status e = launch_features(c, src_pad, g, c->net_x, s);
   if (e != PN_OK) return e;
+  void* own = pn_net_get_stream(c->net);
   pn_net_set_stream(c->net, s);
   e = pn_net_forward(c->net, 1, g.nx8, g.ny8, g.nz8, c->net_x, c->net_y);
+  pn_net_set_stream(c->net, own);
   if (e != PN_OK) return fail(c, e, std::string("network: ") + pn_net_last_error(c->net));
   hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(c->nv)), dim3(kBlock), 0, s, c->u64, (long)c->nv, 0.0);
   hipLaunchKernelGGL(k_net_to_lattice, dim3(grid_for((long long)g.nx * g.ny * g.nz * g.nk)), dim3(kBlock), 0, s,

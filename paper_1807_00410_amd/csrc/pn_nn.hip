@@ -303,6 +303,8 @@ extern "C" pn_status pn_net_create(unsigned long long seed, void* stream, pn_net
   return PN_OK;
 }
 
+extern "C" void* pn_net_get_stream(const pn_net* n) { return n ? (void*)n->stream : nullptr; }
+
 extern "C" pn_status pn_net_set_stream(pn_net* n, void* stream) {
   if (!n) return nfail(nullptr, PN_ERR_ARG, "net is NULL");
   n->stream = (hipStream_t)stream;

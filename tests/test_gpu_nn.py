@@ -189,3 +189,18 @@ def test_training_reduces_loss_and_save_load(tmp_path):
     assert np.array_equal(net2.params(), net.params())
     net.close()
     net2.close()
+
+
+def test_net_load_rejects_foreign_files(tmp_path):
+    from paper_1807_00410_amd.net import Net, NetError
+    net = Net(seed=4)
+    p0 = net.params()
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"not a network file")
+    with pytest.raises(NetError) as e:
+        net.load(bad)
+    assert e.value.status == 1
+    with pytest.raises(NetError):
+        net.load(tmp_path / "missing.bin")
+    assert np.array_equal(net.params(), p0)  # a failed load leaves the parameters
+    net.close()
