@@ -91,6 +91,16 @@ pn_status pn_net_forward(pn_net* net, int B, int nx, int ny, int nz, const uint1
 pn_status pn_net_train_step(pn_net* net, int B, int nx, int ny, int nz, const uint16_t* x,
                             const uint16_t* target, int nout, float lr, double* loss);
 
+/* Training loop: `epochs` passes over nsamples samples given as HOST arrays
+ * of DEVICE pointers (x[i]: [nz][ny][nx][32] bfloat16 input, t[i]:
+ * [nz][ny][nx][nout] bfloat16 target), in a seeded random order, `batch`
+ * samples per step (gathered into staging buffers the call allocates and
+ * frees), learning rate decayed from lr to 0 on a cosine.  *loss_out (may be
+ * NULL): mean loss of the last epoch.  Synchronous. */
+pn_status pn_net_train(pn_net* net, int nsamples, int nx, int ny, int nz, const uint16_t* const* x,
+                       const uint16_t* const* t, int nout, int epochs, int batch, float lr,
+                       unsigned long long seed, double* loss_out);
+
 /* Stream of the network's launches (NULL: the null stream). */
 pn_status pn_net_set_stream(pn_net* net, void* stream);
 void* pn_net_get_stream(const pn_net* net);

@@ -118,6 +118,8 @@ NN_SIGNATURES = [
     ("pn_net_forward", _I, [_V, _I, _I, _I, _I, _V, _V]),
     ("pn_net_train_step", _I, [_V, _I, _I, _I, _I, _V, _V, _I, C.c_float, C.POINTER(C.c_double)]),
     ("pn_net_set_stream", _I, [_V, _V]),
+    ("pn_net_train", _I, [_V, _I, _I, _I, _I, C.POINTER(_V), C.POINTER(_V), _I, _I, _I, C.c_float,
+                          C.c_ulonglong, C.POINTER(C.c_double)]),
     ("pn_net_get_stream", _V, [_V]),
     ("pn_net_grid", _I, [_V, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
     ("pn_net_features", _I, [_V, _V, _V]),

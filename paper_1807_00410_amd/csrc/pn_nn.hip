@@ -3,6 +3,7 @@
 // training step (forward, backward, Adam) on the project's own kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -415,6 +416,57 @@ extern "C" pn_status pn_net_train_step(pn_net* n, int B, int nx, int ny, int nz,
   for (int i = 0; i < nb; ++i) sum += n->lpart_host[i];
   if (loss) *loss = sum / ((double)V * nout);
   return std::isfinite(sum) ? PN_OK : nfail(ERRP, PN_ERR_NONFINITE, "non-finite loss");
+}
+
+// Training loop over samples held as separate device tensors: each epoch
+// visits the samples in a seeded random order, gathers `batch` of them into
+// contiguous staging buffers and takes one training step with a cosine-decayed
+// learning rate.  *loss_out: mean loss of the last epoch.
+extern "C" pn_status pn_net_train(pn_net* n, int nsamples, int nx, int ny, int nz, const uint16_t* const* x,
+                                  const uint16_t* const* t, int nout, int epochs, int batch, float lr,
+                                  unsigned long long seed, double* loss_out) {
+  if (!n || !x || !t || nsamples < 1 || epochs < 1 || batch < 1 || batch > nsamples || !(lr > 0.f))
+    return nfail(ERRP, PN_ERR_ARG, "bad arguments");
+  if (!net_dims_ok(batch, nx, ny, nz) || nout < 1 || nout > kC)
+    return nfail(ERRP, PN_ERR_ARG, "extents must be positive multiples of 8, nout in 1..32");
+  for (int i = 0; i < nsamples; ++i)
+    if (!x[i] || !t[i]) return nfail(ERRP, PN_ERR_ARG, "a sample pointer is NULL");
+  const size_t vx = (size_t)nx * ny * nz * kC, vt = (size_t)nx * ny * nz * nout;
+  uint16_t *bx = nullptr, *bt = nullptr;
+  NN_HIP(hipMalloc(&bx, sizeof(uint16_t) * vx * batch));
+  hipError_t he = hipMalloc(&bt, sizeof(uint16_t) * vt * batch);
+  if (he != hipSuccess) { hipFree(bx); NN_HIP(he); }
+  std::mt19937_64 rng(seed);
+  std::vector<int> order(nsamples);
+  for (int i = 0; i < nsamples; ++i) order[i] = i;
+  const int steps_per_epoch = nsamples / batch;
+  const long long total = (long long)epochs * steps_per_epoch;
+  long long step = 0;
+  pn_status st = PN_OK;
+  double last = 0.0;
+  for (int ep = 0; ep < epochs && st == PN_OK; ++ep) {
+    std::shuffle(order.begin(), order.end(), rng);
+    double sum = 0.0;
+    for (int b = 0; b < steps_per_epoch && st == PN_OK; ++b) {
+      for (int j = 0; j < batch; ++j) {
+        const int i = order[b * batch + j];
+        if (hipMemcpyAsync(bx + vx * j, x[i], sizeof(uint16_t) * vx, hipMemcpyDeviceToDevice, n->stream) != hipSuccess ||
+            hipMemcpyAsync(bt + vt * j, t[i], sizeof(uint16_t) * vt, hipMemcpyDeviceToDevice, n->stream) != hipSuccess)
+          st = nfail(ERRP, PN_ERR_HIP, "staging copy failed");
+      }
+      if (st != PN_OK) break;
+      const float lr_t = (float)(0.5 * lr * (1.0 + std::cos(3.14159265358979323846 * (double)step / (double)total)));
+      double loss = 0.0;
+      st = pn_net_train_step(n, batch, nx, ny, nz, bx, bt, nout, lr_t, &loss);
+      sum += loss;
+      ++step;
+    }
+    last = sum / steps_per_epoch;
+  }
+  hipFree(bx);
+  hipFree(bt);
+  if (st == PN_OK && loss_out) *loss_out = last;
+  return st;
 }
 
 #undef ERRP

@@ -164,6 +164,17 @@ class Net:
         self._check(self.lib.pn_net_forward(self.n, B, nx, ny, nz, _p(x, torch.bfloat16), _p(y)))
         return y
 
+    def train(self, xs, ts, epochs, batch, lr, seed=0):
+        """pn_net_train over lists of per-sample tensors x [1, nz, ny, nx, 32]
+        and target [1, nz, ny, nx, nout]; returns the last epoch's mean loss."""
+        _, nx, ny, nz = _dims(xs[0])
+        xp = (C.c_void_p * len(xs))(*[_p(v, torch.bfloat16).value for v in xs])
+        tp = (C.c_void_p * len(ts))(*[_p(v, torch.bfloat16).value for v in ts])
+        loss = C.c_double()
+        self._check(self.lib.pn_net_train(self.n, len(xs), nx, ny, nz, xp, tp, int(ts[0].shape[-1]), int(epochs),
+                                          int(batch), float(lr), int(seed), C.byref(loss)))
+        return loss.value
+
     def train_step(self, x, target, lr):
         B, nx, ny, nz = _dims(x)
         loss = C.c_double()

@@ -204,3 +204,19 @@ def test_net_load_rejects_foreign_files(tmp_path):
         net.load(tmp_path / "missing.bin")
     assert np.array_equal(net.params(), p0)  # a failed load leaves the parameters
     net.close()
+
+
+def test_net_train_loop():
+    from paper_1807_00410_amd.net import Net
+    rng = np.random.default_rng(9)
+    xs, ts = [], []
+    for _ in range(8):
+        xh = exact(rng, (1, 8, 8, 8, KC), 0.5)
+        xs.append(bf(xh))
+        ts.append(bf(0.3 + 0.5 * xh[..., :16]))
+    net = Net(seed=5)
+    first = np.mean([net.train_step(xs[i], ts[i], 0.0) for i in range(8)])
+    last = net.train(xs, ts, epochs=15, batch=2, lr=5e-3, seed=1)
+    print("train loop: loss %.4g -> %.4g" % (first, last))
+    assert last < 0.7 * first
+    net.close()
