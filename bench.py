@@ -278,7 +278,7 @@ def main():
         "config": {"workload": "P%d nebula %d^3 (32 Gaussian blobs x fBm, sigma_t in [0,200], albedo 0.95, "
                                "g=%g, 2 point sources), vacuum boundary, tol %g"
                                % (m.order, args.n, m.g, args.tol),
-                   "unknowns": s.n, "solver": "FP32 CG on the normal equations + FP64 dots/refinement (plain)",
+                   "unknowns": s.n, "solver": "FP32 CG on the row-equilibrated normal equations + FP64 dots/refinement (plain)",
                    "inner_tol": args.inner_tol, "zchunk": zchunk},
         "iters": infos[-1]["inner_iters"],
         "outer_iters": infos[-1]["outer_iters"],

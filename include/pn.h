@@ -117,15 +117,22 @@ typedef struct {
 #define PN_LEARNED_GUESS_CORRECT 2
 
 /* Krylov variant of the FP32 inner solve.  CGLS: the residual-based CGLS
- * form (r <- r - alpha q fused into s = A^T r).  AUTO and CG: CG on the normal
+ * form (r <- r - alpha q fused into s = A^T r).  CG: CG on the normal
  * equations A^T A u = A^T Q with the recursive normal residual
  * (s <- s - alpha A^T q, ||r||^2 <- ||r||^2 - alpha gamma; 10 vector passes
  * per iteration, and the A^T pass streams one vector instead of two), on
- * whichever stencil is in use.  The FP64 refinement checks the true residual
- * either way. */
+ * whichever stencil is in use.  CG_EQ: the same on the row-equilibrated
+ * system W A u = W Q, W = diag(1 / ||row of A||_2) (the row norm taken with
+ * every transport neighbour present, formed from the medium inside the
+ * kernels: no extra memory traffic); the inner stop then tests the W-weighted
+ * residual.  Needs the register-window stencil (PN_ERR_ARG with pn_set_tiles
+ * or PN_FP64).  AUTO: CG_EQ on the register-window stencil, CG on the
+ * LDS-tiled one.  The FP64 refinement checks the true, unweighted residual
+ * ||Q - A x|| in every case. */
 #define PN_VARIANT_AUTO 0
 #define PN_VARIANT_CGLS 1
 #define PN_VARIANT_CG 2
+#define PN_VARIANT_CG_EQ 3
 
 #define PN_MAX_HISTORY 64
 typedef struct {
@@ -171,6 +178,14 @@ pn_status pn_layout_query(const pn_ctx* ctx, pn_layout* layout);
  * the sign of the transport part (it is skew-symmetric).  x and y are device
  * FP32 vectors of n_unknowns entries and must not overlap.  Asynchronous. */
 pn_status pn_apply(pn_ctx* ctx, const float* x, float* y, int transpose);
+
+/* Row weights of the equilibrated CG variant (PN_VARIANT_CG_EQ): w[i] =
+ * 1 / (d_i^2 + sum of the squared transport entries of row i with every
+ * neighbour present), d_i the diagonal -- 1 / ||row i of A||_2^2 away from
+ * the boundary, smaller next to a vacuum boundary, where the row loses
+ * entries.  w: DEVICE FP32, packed layout, n_unknowns entries.  Async on the
+ * context stream. */
+pn_status pn_row_weights(pn_ctx* ctx, float* w);
 
 /* Same operator evaluated in FP64 (couplings, interpolation and products in
  * double) on FP64 vectors.  Asynchronous. */

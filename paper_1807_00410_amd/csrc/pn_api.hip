@@ -554,6 +554,20 @@ extern "C" pn_status pn_apply(pn_ctx* c, const float* x, float* y, int transpose
   return PN_OK;
 }
 
+extern "C" pn_status pn_row_weights(pn_ctx* c, float* w) {
+  if (!c) return PN_ERR_ARG;
+  if (!w) return fail(c, PN_ERR_ARG, "w is NULL");
+  // W applied to the all-ones vector
+  hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, w, (long)c->n, 1.0f);
+  PN_HIP(hipGetLastError());
+  PN_HIP((launch_pack<float, float, 0>(c, w, c->p32, c->stream)));
+  StencilArgs a = base_args(c);
+  a.x = c->p32; a.y = c->q32; a.partials = c->partials;
+  PN_HIP((launch_stencil<float, M_EQS, float>(c, a, c->stream)));
+  PN_HIP((launch_pack<float, float, 1>(c, c->q32, w, c->stream)));
+  return PN_OK;
+}
+
 extern "C" pn_status pn_apply64(pn_ctx* c, const double* x, double* y, int transpose) {
   if (!c) return PN_ERR_ARG;
   if (!x || !y) return fail(c, PN_ERR_ARG, "x or y is NULL");
@@ -646,13 +660,18 @@ static hipError_t enqueue_iteration(pn_ctx* c, T* d, T* p, T* q, T* s, const T* 
 // One iteration of CG on the normal equations (FP32 vectors; LDS-tiled or
 // register-window stencil):
 // q = A p | alpha | s -= alpha A^T q | beta | x += alpha p, p = s + beta p.
-static hipError_t enqueue_iteration_cg(pn_ctx* c, float* d, float* p, float* q, float* s, hipStream_t st) {
+// Row-equilibrated (eq, register-window stencil only): CG on A^T W A u = A^T W r
+// with W = diag(1 / ||row of A||^2): q = W A p, alpha = gamma / <A p, W A p>,
+// the rest unchanged.
+static hipError_t enqueue_iteration_cg(pn_ctx* c, float* d, float* p, float* q, float* s, bool eq, hipStream_t st) {
   StencilArgs a = base_args(c);
   a.st = c->st;
   a.partials = c->partials;
   a.x = p; a.y = q; a.tsign = 1.0;
   const int nb = c->use_lds ? c->lnblocks : c->nblocks;
-  hipError_t e = c->use_lds ? launch_lds(c, M_APPLY, true, a, st) : launch_stencil<float, M_APPLY, float>(c, a, st);
+  hipError_t e = c->use_lds ? launch_lds(c, M_APPLY, true, a, st)
+                 : eq       ? launch_stencil<float, M_APPLY_EQ, float>(c, a, st)
+                            : launch_stencil<float, M_APPLY, float>(c, a, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fin_alpha_cg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, nb);
   a.x = q; a.y = s; a.tsign = -1.0;
@@ -664,12 +683,12 @@ static hipError_t enqueue_iteration_cg(pn_ctx* c, float* d, float* p, float* q, 
   return hipGetLastError();
 }
 
-static pn_status build_graph_cg(pn_ctx* c, int iters, hipGraphExec_t* exec) {
+static pn_status build_graph_cg(pn_ctx* c, int iters, bool eq, hipGraphExec_t* exec) {
   hipGraph_t g = nullptr;
   PN_HIP(hipStreamBeginCapture(c->sstream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
   for (int i = 0; i < iters && e == hipSuccess; ++i)
-    e = enqueue_iteration_cg(c, c->d32, c->p32, c->q32, c->s32, c->sstream);
+    e = enqueue_iteration_cg(c, c->d32, c->p32, c->q32, c->s32, eq, c->sstream);
   hipError_t e2 = hipStreamEndCapture(c->sstream, &g);
   if (e != hipSuccess) { if (g) hipGraphDestroy(g); return fail(c, PN_ERR_HIP, std::string("capture: ") + hipGetErrorString(e)); }
   if (e2 != hipSuccess) return fail(c, PN_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
@@ -869,16 +888,19 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
   // vector); otherwise CGLS with the recursive residual r (11 passes, r
   // ping-pong, the A^T pass streams two).
   const bool cg = (sizeof(T) == 4) && o.variant != PN_VARIANT_CGLS;
+  // row equilibration: AUTO and CG_EQ on the register-window stencil
+  const bool eq = cg && !c->use_lds && (o.variant == PN_VARIANT_AUTO || o.variant == PN_VARIANT_CG_EQ);
   if (cg) {
     gexec = &c->gexec_cg;
     giters = &c->giters_cg;
   }
   int gi = o.graph_iters < 2 ? 2 : (o.graph_iters + 1) & ~1;  // even: r ends in r0
-  if (*gexec == nullptr || *giters != gi) {
+  if (*gexec == nullptr || *giters != gi || (cg && c->gcg_eq != (int)eq)) {
     if (*gexec) { hipGraphExecDestroy(*gexec); *gexec = nullptr; }
-    pn_status e = cg ? build_graph_cg(c, gi, gexec) : build_graph<T>(c, gi, d, p, q, s, r0, r1, gexec);
+    pn_status e = cg ? build_graph_cg(c, gi, eq, gexec) : build_graph<T>(c, gi, d, p, q, s, r0, r1, gexec);
     if (e != PN_OK) return e;
     *giters = gi;
+    if (cg) c->gcg_eq = (int)eq;
   }
   hipStream_t ss = c->sstream;
   DevState init;
@@ -955,7 +977,18 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     if (itol >= 1.0) itol = 0.5;
     hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, d, (long)c->nv, T(0));
     StencilArgs a = base_args(c);
-    a.x = r0; a.y = s; a.tsign = -1.0; a.partials = c->partials;
+    a.partials = c->partials;
+    const T* rs = r0;
+    if constexpr (sizeof(T) == 4) {
+      if (eq) {  // r1 = W r0; the inner solve tracks <r, W r>
+        a.x = r0; a.y = r1;
+        PN_HIP((launch_stencil<float, M_EQS, float>(c, a, ss)));
+        hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials, c->nblocks);
+        PN_HIP(hipGetLastError());
+        rs = r1;
+      }
+    }
+    a.x = rs; a.y = s; a.tsign = -1.0;
     if (cg && c->use_lds) PN_HIP(launch_lds(c, M_APPLY, true, a, ss));
     else PN_HIP((launch_stencil<T, M_APPLY, T>(c, a, ss)));
     hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials,
@@ -994,6 +1027,9 @@ extern "C" pn_status pn_solve(pn_ctx* c, const float* rhs, double* x, double tol
   if (o.precision != PN_FP32_IR && o.precision != PN_FP64) return fail(c, PN_ERR_ARG, "unknown precision");
   if (o.learned < PN_LEARNED_OFF || o.learned > PN_LEARNED_GUESS_CORRECT)
     return fail(c, PN_ERR_ARG, "unknown learned mode");
+  if (o.variant < PN_VARIANT_AUTO || o.variant > PN_VARIANT_CG_EQ) return fail(c, PN_ERR_ARG, "unknown variant");
+  if (o.variant == PN_VARIANT_CG_EQ && (c->use_lds || o.precision != PN_FP32_IR))
+    return fail(c, PN_ERR_ARG, "the equilibrated CG variant needs FP32_IR and the register-window stencil");
   if (info) std::memset(info, 0, sizeof(*info));
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t ss = c->sstream;

@@ -58,6 +58,7 @@ struct pn_batch {
   hipGraphExec_t gexec = nullptr;
   int giters = 0;
   bool gcg = false;
+  bool geq = false;
   long long unknowns = 0;
   std::string err;
 };
@@ -151,10 +152,11 @@ hipError_t fin_all(const pn_batch* b, hipStream_t s) {
 }
 
 // One Krylov iteration of every running system, as pn_solve's FP32 inner
-// solve: CG on the normal equations (s -= alpha A^T q), or CGLS (r ping-pong
-// rin -> rout, r' = r - alpha q fused into s = A^T r').
-hipError_t enqueue_batch_iteration(const pn_batch* b, bool cg, int rin, int rout, hipStream_t s) {
-  hipError_t e = stencil_all(b, K_F32_APPLY, roles(b, BV_P, -1, BV_Q, -1, 1.0, 1), s);
+// solve: CG on the normal equations (s -= alpha A^T q; eq: row-equilibrated,
+// q = W A p), or CGLS (r ping-pong rin -> rout, r' = r - alpha q fused into
+// s = A^T r').
+hipError_t enqueue_batch_iteration(const pn_batch* b, bool cg, bool eq, int rin, int rout, hipStream_t s) {
+  hipError_t e = stencil_all(b, (cg && eq) ? K_F32_APPLY_EQ : K_F32_APPLY, roles(b, BV_P, -1, BV_Q, -1, 1.0, 1), s);
   if (cg) {
     if (e == hipSuccess) e = fin_all<BF_ALPHA_CG>(b, s);
     if (e == hipSuccess) e = stencil_all(b, K_F32_SUPD, roles(b, BV_Q, -1, BV_S, -1, -1.0, 1), s);
@@ -195,15 +197,15 @@ pn_status compact(pn_batch* b, const std::vector<char>& keep, hipStream_t s) {
   return PN_OK;
 }
 
-pn_status build_batch_graph(pn_batch* b, int iters, bool cg) {
-  if (b->gexec && b->giters == iters && b->gcg == cg) return PN_OK;
+pn_status build_batch_graph(pn_batch* b, int iters, bool cg, bool eq) {
+  if (b->gexec && b->giters == iters && b->gcg == cg && b->geq == eq) return PN_OK;
   if (b->gexec) { hipGraphExecDestroy(b->gexec); b->gexec = nullptr; b->giters = 0; }
   hipGraph_t g = nullptr;
   B_HIP(hipStreamBeginCapture(b->sstream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
   for (int i = 0; i < iters && e == hipSuccess; ++i)
-    e = (i & 1) ? enqueue_batch_iteration(b, cg, BV_R1, BV_R0, b->sstream)
-                : enqueue_batch_iteration(b, cg, BV_R0, BV_R1, b->sstream);
+    e = (i & 1) ? enqueue_batch_iteration(b, cg, eq, BV_R1, BV_R0, b->sstream)
+                : enqueue_batch_iteration(b, cg, eq, BV_R0, BV_R1, b->sstream);
   hipError_t e2 = hipStreamEndCapture(b->sstream, &g);
   if (e != hipSuccess) {
     if (g) hipGraphDestroy(g);
@@ -215,6 +217,7 @@ pn_status build_batch_graph(pn_batch* b, int iters, bool cg) {
   if (e3 != hipSuccess) return bfail(b, PN_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e3));
   b->giters = iters;
   b->gcg = cg;
+  b->geq = eq;
   return PN_OK;
 }
 
@@ -424,6 +427,9 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
   if (o.max_iter < 1 || o.max_refine < 0 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0))
     return bfail(b, PN_ERR_ARG, "invalid solve options");
   if (o.precision != PN_FP32_IR) return bfail(b, PN_ERR_ARG, "the batched solve runs FP32 with FP64 refinement only");
+  if (o.variant < PN_VARIANT_AUTO || o.variant > PN_VARIANT_CG_EQ) return bfail(b, PN_ERR_ARG, "unknown variant");
+  const bool cg = o.variant != PN_VARIANT_CGLS;
+  const bool eq = o.variant == PN_VARIANT_AUTO || o.variant == PN_VARIANT_CG_EQ;
   if (info) std::memset(info, 0, sizeof(pn_solve_info) * b->nsys);
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t ss = b->sstream;
@@ -511,12 +517,18 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
     if (cs != PN_OK) return cs;
     // inner solves  A d = r0  from d = 0
     B_HIP(vec_all<BO_ZERO_D>(b, ss));
-    B_HIP(stencil_all(b, K_F32_APPLY, roles(b, BV_R0, -1, BV_S, -1, -1.0, 0), ss));
+    int rs = BV_R0;
+    if (eq) {  // r1 = W r0; the inner solves track <r, W r>
+      B_HIP(stencil_all(b, K_F32_EQS, roles(b, BV_R0, -1, BV_R1, -1, 1.0, 0), ss));
+      B_HIP(fin_all<BF_RR>(b, ss));
+      rs = BV_R1;
+    }
+    B_HIP(stencil_all(b, K_F32_APPLY, roles(b, rs, -1, BV_S, -1, -1.0, 0), ss));
     B_HIP(fin_all<BF_INIT>(b, ss));
     B_HIP(vec_all<BO_COPY_SP>(b, ss));
     for (;;) {
       if (!b->gexec) {
-        pn_status e = build_batch_graph(b, gi, o.variant != PN_VARIANT_CGLS);
+        pn_status e = build_batch_graph(b, gi, cg, eq);
         if (e != PN_OK) return e;
       }
       B_HIP(hipGraphLaunch(b->gexec, ss));

@@ -87,6 +87,7 @@ struct pn_ctx {
   size_t lds_bytes = 0, lds_max = 0;
   hipGraphExec_t gexec_cg = nullptr;  // captured CG-on-normal-equations iterations
   int giters_cg = 0;
+  int gcg_eq = 0;                     // gexec_cg holds the row-equilibrated form
   // learned initial guess / correction (pn_attach_net)
   pn_net* net = nullptr;
   uint16_t* net_x = nullptr;   // network input [cells8][32] bfloat16
@@ -157,7 +158,11 @@ inline hipError_t launch_stencil(const pn_ctx* c, const StencilArgs& a, hipStrea
   const bool per = c->bc == PN_BC_PERIODIC;
   const bool norm = !(MODE == M_APPLY && a.partials == nullptr);
   int kind;
-  if constexpr (sizeof(T) == 4) kind = (MODE == M_APPLY) ? K_F32_APPLY : (MODE == M_SUPD ? K_F32_SUPD : K_F32_TRANSR);
+  if constexpr (sizeof(T) == 4)
+    kind = (MODE == M_APPLY) ? K_F32_APPLY
+         : (MODE == M_SUPD) ? K_F32_SUPD
+         : (MODE == M_APPLY_EQ) ? K_F32_APPLY_EQ
+         : (MODE == M_EQS) ? K_F32_EQS : K_F32_TRANSR;
   else if constexpr (MODE == M_APPLY) kind = K_F64_APPLY;
   else if constexpr (MODE == M_TRANSR) kind = K_F64_TRANSR;
   else kind = (sizeof(TO) == 4) ? K_F64_RESID32 : K_F64_RESID64;

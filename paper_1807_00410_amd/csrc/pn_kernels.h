@@ -58,8 +58,9 @@ struct DevState {
 };
 
 // M_SUPD: s <- s - alpha * op(x) (the normal-equation residual update of CG
-// on A^T A), used by the LDS-tiled kernel.
-enum Mode { M_APPLY = 0, M_TRANSR = 1, M_RESID = 2, M_SUPD = 3 };
+// on A^T A).  M_APPLY_EQ / M_EQS: the row-equilibrated forms (w = 1 / ||row
+// of A||^2 per unknown, formed from the medium in the kernel).
+enum Mode { M_APPLY = 0, M_TRANSR = 1, M_RESID = 2, M_SUPD = 3, M_APPLY_EQ = 4, M_EQS = 5 };
 
 // Internal vectors live on a padded lattice shared by every coefficient:
 // coefficient k occupies [k*cs, (k+1)*cs); lattice point (x, y, z) of any
@@ -161,6 +162,11 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 //   M_TRANSR r' = r - alpha q, y = A^T r'      [writes r' to y2; ||y||^2, ||r'||^2]
 //   M_RESID  y = Q - A x                       [||y||^2, ||Q||^2]
 //   M_SUPD   y = y - alpha op(x)               [||y||^2]
+//   M_APPLY_EQ  y = W A x                      [<A x, W A x>]
+//   M_EQS    y = W x                           [<x, W x>]
+// W is diagonal: w = 1 / (d^2 + sum of the squared transport entries of the
+// row), d the row's diagonal -- the inverse squared 2-norm of the row of A
+// away from the boundary.
 template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
 __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) {
   using TB = Table<N>;
@@ -181,6 +187,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
   T alpha = T(0);
   if constexpr (MODE == M_TRANSR || MODE == M_SUPD) alpha = T(a.st->alpha);
   const T tinvh = T(a.tsign * a.invh);
+  const T invh2 = T(a.invh * a.invh);
   const long long cs = a.cs;
 
   // Lane offsets inside a padded plane (own point and the four in-plane
@@ -341,6 +348,14 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
                 const long long base = cbase(K, zo);
                 const T dg = fmadd<T>(T(a.omg[band_of(K)]), css[c], csa[c]);
                 T out = fmadd<T>(tinvh, acc[K], dg * cur[K]);
+                if constexpr (MODE == M_EQS) out = cur[K];
+                if constexpr (MODE == M_APPLY_EQ || MODE == M_EQS) {
+                  constexpr T rc2 = T(TB::row_c2(K));
+                  const T w = __builtin_amdgcn_rcpf(fmadd<T>(dg, dg, invh2 * rc2));
+                  const T wo = w * out;
+                  cn0 = fmadd<T>(wo, out, cn0);
+                  out = wo;
+                }
                 if constexpr (MODE == M_RESID) {
                   const T q = T(ldb(RHS + base, orhs));
                   out = q - out;
@@ -348,7 +363,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
                 }
                 if constexpr (MODE == M_SUPD) out = fmadd<T>(-alpha, out, T(ldb(Y + base, oo)));
                 stb(Y + base, oo, TO(out));
-                if constexpr (NORM) cn0 = fmadd<T>(out, out, cn0);
+                if constexpr (NORM && MODE != M_APPLY_EQ && MODE != M_EQS) cn0 = fmadd<T>(out, out, cn0);
                 if constexpr (MODE == M_TRANSR) {
                   stb(Y2 + base, oo, TO(cur[K]));
                   cn1 = fmadd<T>(cur[K], cur[K], cn1);
@@ -356,7 +371,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
               }
             });
             if constexpr (NORM) nrm0 += double(cn0);
-            if constexpr (MODE != M_APPLY) nrm1 += double(cn1);
+            if constexpr (MODE == M_TRANSR || MODE == M_RESID) nrm1 += double(cn1);
           }
         }
       });
@@ -377,7 +392,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
 template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
 __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil(const StencilArgs a) {
   // In the Krylov loop the A p launch also ends once the stop flag is up.
-  if (a.st != nullptr && (a.st->done || (MODE == M_APPLY && a.st->stop))) return;
+  if (a.st != nullptr && (a.st->done || ((MODE == M_APPLY || MODE == M_APPLY_EQ) && a.st->stop))) return;
   stencil_body<N, T, MODE, TO, PER, NORM>(a, xcd_remap(blockIdx.x, a.nblocks));
 }
 
@@ -411,7 +426,7 @@ __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil_batch(const 
   const int2 w = bl.work[xcd_remap(blockIdx.x, bl.nwork)];
   const SysArgs* __restrict__ s = bl.sys + w.x;
   DevState* st = s->a.st;
-  if (st->frozen || (bl.gate && (st->done || (MODE == M_APPLY && st->stop)))) return;
+  if (st->frozen || (bl.gate && (st->done || ((MODE == M_APPLY || MODE == M_APPLY_EQ) && st->stop)))) return;
   StencilArgs a = s->a;
   a.x = s->vec[bl.ix];
   a.x2 = bl.ix2 >= 0 ? s->vec[bl.ix2] : nullptr;
@@ -541,6 +556,13 @@ __device__ __forceinline__ void fin_beta_cg(DevState* st, const double* partials
   }
 }
 
+// After r~ = W r (equilibrated CG):  the tracked residual norm is <r, W r>.
+__device__ __forceinline__ void fin_rr(DevState* st, const double* partials, int n) {
+  double rr, unused;
+  grid_sum2(partials, n, rr, unused);
+  if (threadIdx.x == 0) st->rr = rr;
+}
+
 // After r = Q - A x (FP64):  true residual and ||Q||^2.
 __device__ __forceinline__ void fin_resid(DevState* st, const double* partials, int n) {
   double rr, bb;
@@ -558,6 +580,7 @@ static __global__ void __launch_bounds__(kBlock) k_fin_init(DevState* st, const 
 static __global__ void __launch_bounds__(kBlock) k_fin_alpha_cg(DevState* st, const double* partials, int n) { fin_alpha_cg(st, partials, n); }
 static __global__ void __launch_bounds__(kBlock) k_fin_beta_cg(DevState* st, const double* partials, int n) { fin_beta_cg(st, partials, n); }
 static __global__ void __launch_bounds__(kBlock) k_fin_resid(DevState* st, const double* partials, int n) { fin_resid(st, partials, n); }
+static __global__ void __launch_bounds__(kBlock) k_fin_rr(DevState* st, const double* partials, int n) { fin_rr(st, partials, n); }
 
 // ---------------------------------------------------------------- vector --
 // x += alpha p;  p = s + beta p
@@ -677,7 +700,7 @@ static __global__ void __launch_bounds__(kBlock) k_check_finite(const float* __r
 
 // ------------------------------------------------------- batch (scalars) --
 // One block per system; a finished (frozen) system is skipped.
-enum BatchFin { BF_ALPHA = 0, BF_BETA = 1, BF_INIT = 2, BF_RESID = 3, BF_ALPHA_CG = 4, BF_BETA_CG = 5 };
+enum BatchFin { BF_ALPHA = 0, BF_BETA = 1, BF_INIT = 2, BF_RESID = 3, BF_ALPHA_CG = 4, BF_BETA_CG = 5, BF_RR = 6 };
 
 template <int WHICH>
 __global__ void __launch_bounds__(kBlock) k_fin_batch(const SysArgs* __restrict__ sys) {
@@ -691,6 +714,7 @@ __global__ void __launch_bounds__(kBlock) k_fin_batch(const SysArgs* __restrict_
   else if constexpr (WHICH == BF_INIT) fin_init(st, p, n, st->itol2);
   else if constexpr (WHICH == BF_ALPHA_CG) fin_alpha_cg(st, p, n);
   else if constexpr (WHICH == BF_BETA_CG) fin_beta_cg(st, p, n);
+  else if constexpr (WHICH == BF_RR) fin_rr(st, p, n);
   else fin_resid(st, p, n);
 }
 

@@ -15,7 +15,9 @@ enum Kind {
   K_F64_TRANSR = 3,  // double -> double
   K_F64_RESID32 = 4, // double x, float Q -> float r = Q - A x
   K_F64_RESID64 = 5, // double x, float Q -> double r
-  K_F32_SUPD = 6     // float: s = s - alpha op(x) (CG on the normal equations)
+  K_F32_SUPD = 6,    // float: s = s - alpha op(x) (CG on the normal equations)
+  K_F32_APPLY_EQ = 7,// float: y = W A x (row-equilibrated CG)
+  K_F32_EQS = 8      // float: y = W x
 };
 
 template <int N, typename T, int MODE, typename TO>
@@ -41,6 +43,8 @@ hipError_t launch_order(int kind, bool per, bool norm, const StencilArgs& a, hip
     case K_F64_RESID32: return launch_flavour<N, double, M_RESID, float>(per, true, a, s);
     case K_F64_RESID64: return launch_flavour<N, double, M_RESID, double>(per, true, a, s);
     case K_F32_SUPD: return launch_flavour<N, float, M_SUPD, float>(per, true, a, s);
+    case K_F32_APPLY_EQ: return launch_flavour<N, float, M_APPLY_EQ, float>(per, true, a, s);
+    case K_F32_EQS: return launch_flavour<N, float, M_EQS, float>(per, true, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -61,6 +65,8 @@ hipError_t launch_batch_order(int kind, bool per, const BatchLaunch& bl, hipStre
     case K_F32_APPLY: return launch_batch_flavour<N, float, M_APPLY, float>(per, bl, s);
     case K_F32_TRANSR: return launch_batch_flavour<N, float, M_TRANSR, float>(per, bl, s);
     case K_F32_SUPD: return launch_batch_flavour<N, float, M_SUPD, float>(per, bl, s);
+    case K_F32_APPLY_EQ: return launch_batch_flavour<N, float, M_APPLY_EQ, float>(per, bl, s);
+    case K_F32_EQS: return launch_batch_flavour<N, float, M_EQS, float>(per, bl, s);
     case K_F64_RESID32: return launch_batch_flavour<N, double, M_RESID, float>(per, bl, s);
     default: return hipErrorInvalidValue;
   }

@@ -197,6 +197,16 @@ struct Table {
     return q;
   }
   static constexpr Need need = make_need();
+
+  // Sum of the squared transport entries of row k of A in units of 1/h^2:
+  // each coupling (k, kp, d, c) puts +c/h and -c/h into the row (the two
+  // staggered neighbours along d), so 2 c^2 per coupling.
+  static constexpr double row_c2(int k) {
+    double s = 0.0;
+    for (int i = 0; i < NCPL; ++i)
+      if (cpl.v[i].k == k) s += 2.0 * cpl.v[i].c * cpl.v[i].c;
+    return s;
+  }
 };
 
 }  // namespace pn

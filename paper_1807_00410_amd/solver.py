@@ -95,6 +95,12 @@ class Solver:
         self._check(self.lib.pn_apply(self.ctx, _ptr(x, torch.float32), _ptr(y, torch.float32), int(transpose)))
         return y
 
+    def row_weights(self):
+        """Diagonal of W in the equilibrated CG variant (pn_row_weights)."""
+        w = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        self._check(self.lib.pn_row_weights(self.ctx, _ptr(w, torch.float32)))
+        return w
+
     def apply64(self, x, y=None, transpose=False):
         y = torch.empty_like(x) if y is None else y
         self._check(self.lib.pn_apply64(self.ctx, _ptr(x, torch.float64), _ptr(y, torch.float64), int(transpose)))
@@ -189,7 +195,7 @@ def _opts(lib, precision, max_iter, max_refine, inner_tol, use_guess, graph_iter
     opts.inner_tol = float(inner_tol)
     opts.use_guess = int(bool(use_guess))
     opts.graph_iters = int(graph_iters)
-    opts.variant = {"auto": 0, "cgls": 1, "cg": 2}[variant]
+    opts.variant = {"auto": 0, "cgls": 1, "cg": 2, "cg_eq": 3}[variant]
     return opts
 
 
