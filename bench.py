@@ -6,10 +6,15 @@ One step = one complete solve A u = Q from u = 0 to ||Q - A u|| <= 1e-8 ||Q||
 residual), inputs resident in HBM.  Prints one JSON line.
 
 Also reported (JSON keys):
-  roofline      the stencil apply (the dominant kernel of the Krylov loop),
-                timed with HIP events on the solver stream: algorithmic bytes
-                per apply (8 B per unknown: read x, write y; plus 8 B per
-                cell of medium) / mean apply time, against the 8 TB/s HBM peak.
+  roofline      the kernel of the Krylov loop that takes the most time per
+                iteration (s -= alpha A^T q at P5 128^3), timed in its in-loop
+                form with HIP events on the stream it runs on: algorithmic
+                bytes per launch / mean launch time, against the 8 TB/s HBM
+                peak; traffic = HBM bytes per launch from the committed
+                rocprofv3 FETCH_SIZE / WRITE_SIZE summary when it was taken
+                on the current kernel sources.
+  loop_kernels  the same figures for every kernel of the loop (the plain
+                apply, q = W A p, s -= alpha A^T q, the x/p update).
   cpu_baseline  the FP64 oracle (NumPy, one thread) timed for one CGLS
                 iteration at the full size, scaled by the GPU solve's
                 iteration count.
@@ -36,17 +41,28 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_hash, ms_per_apply):
-    """HBM bytes per apply from the committed rocprofv3 counter summary, or
-    None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "stencil_p5_128_counters.json")
+def load_traffic(kernel_hash, kernel):
+    """HBM bytes per launch of one loop kernel from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since the
+    counters were taken."""
+    path = os.path.join(ROOT, "profiles", "krylov_p5_128_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
     if d.get("source_hash") != kernel_hash:
         return None
-    return d.get("hbm_bytes_per_apply")
+    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+
+
+# algorithmic HBM bytes of the Krylov-loop kernels: per unknown (FP32 vector
+# elements read + written) and whether the medium (8 B per cell) is read
+LOOP_KERNELS = (
+    ("apply", 8, True, "k_stencil<5,float,APPLY>: y = A x"),
+    ("apply_eq", 8, True, "k_stencil<5,float,APPLY_EQ>: q = W A p, <A p, W A p> partials"),
+    ("supd", 12, True, "k_stencil<5,float,SUPD>: s -= alpha A^T q, ||s||^2 partials"),
+    ("update", 20, False, "k_update_xp<float>: x += alpha p, p = s + beta p"),
+)
 
 
 def cpu_baseline(medium, gpu_iters):
@@ -202,14 +218,21 @@ def main():
     total = time.perf_counter() - t_all
     sec = sum(times) / len(times)
 
-    # stencil roofline (HIP events on the solver stream)
+    # Krylov-loop kernels in their in-loop form (HIP events on their stream)
     ms_apply = s.bench_apply(args.apply_iters, transpose=False)
     ms_apply_t = s.bench_apply(args.apply_iters, transpose=True)
     cells = m.dims[0] * m.dims[1] * m.dims[2]
-    alg_bytes = 8 * s.n + 8 * cells
-    achieved = alg_bytes / (ms_apply * 1e-3) / 1e9
     khash = source_hash()
-    traffic = load_traffic(khash, ms_apply)
+    loop = {}
+    for name, per_unknown, medium, desc in LOOP_KERNELS:
+        ms = s.bench_kernel(name, args.apply_iters)
+        alg = per_unknown * s.n + (8 * cells if medium else 0)
+        ach = alg / (ms * 1e-3) / 1e9
+        loop[name] = {"kernel": desc, "ms": ms, "algorithmic_bytes_per_launch": alg, "achieved": ach,
+                      "frac": ach / HBM_PEAK_GBS, "traffic": load_traffic(khash, name)}
+        print("[bench] %-8s %.4f ms  %.0f GB/s algorithmic" % (name, ms, ach), file=sys.stderr, flush=True)
+    # the dominant kernel: the most time per iteration of the default solve
+    dom = max(("apply_eq", "supd", "update"), key=lambda k: loop[k]["ms"])
 
     fp64 = None
     if not args.no_fp64:
@@ -289,10 +312,11 @@ def main():
         "fp64_krylov": fp64,
         "fp32_krylov_no_refinement": fp32_single,
         "learned_mixed": learned,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes_per_apply": alg_bytes,
-                     "kernel": "k_stencil<5,float,APPLY> (padded lattice)", "source_hash": khash},
+        "roofline": {"bound": "hbm", "achieved": loop[dom]["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": loop[dom]["frac"], "traffic": loop[dom]["traffic"],
+                     "algorithmic_bytes_per_launch": loop[dom]["algorithmic_bytes_per_launch"],
+                     "ms_per_launch": loop[dom]["ms"], "kernel": loop[dom]["kernel"], "source_hash": khash},
+        "loop_kernels": loop,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, ~20-30 s)", file=sys.stderr, flush=True)

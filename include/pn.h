@@ -213,6 +213,28 @@ pn_status pn_solve(pn_ctx* ctx, const float* rhs, double* x, double tol,
  * apply to *ms_per_apply (host).  Synchronous.  For benchmarking. */
 pn_status pn_bench_apply(pn_ctx* ctx, int iters, int transpose, double* ms_per_apply);
 
+/* Times one kernel of the FP32 Krylov loop in its in-loop form on the
+ * library's padded workspace, with HIP events on the context stream; writes
+ * the mean milliseconds per launch.  The plain applies run `iters` times back
+ * to back; the in-loop kernels run inside `iters` iterations of the loop's
+ * own kernel sequence (q = W A p, s -= alpha A^T q, x/p update: the cache
+ * state of a solve), timed by events around the requested one.  kernel:
+ *   PN_KERNEL_APPLY      y = A x (no reduction; as pn_bench_apply)
+ *   PN_KERNEL_APPLY_T    y = A^T x
+ *   PN_KERNEL_APPLY_EQ   q = W A p with the FP64 partials of <A p, W A p>
+ *   PN_KERNEL_SUPD       s -= alpha A^T q with the FP64 partials of ||s||^2
+ *   PN_KERNEL_UPDATE     x += alpha p, p = s + beta p
+ * Resets the device scalars (the next pn_solve re-initialises them) and
+ * overwrites the workspace.  PN_ERR_ARG for an unknown kernel, or for the
+ * in-loop kernels while the LDS-tiled stencil is selected.  Synchronous.
+ * For benchmarking. */
+#define PN_KERNEL_APPLY 0
+#define PN_KERNEL_APPLY_T 1
+#define PN_KERNEL_APPLY_EQ 2
+#define PN_KERNEL_SUPD 3
+#define PN_KERNEL_UPDATE 4
+pn_status pn_bench_kernel(pn_ctx* ctx, int kernel, int iters, double* ms);
+
 /* Launch tuning: planes of z handled per thread block in the stencil apply
  * (0 = automatic).  Results do not depend on it (bitwise). */
 pn_status pn_set_zchunk(pn_ctx* ctx, int zchunk);

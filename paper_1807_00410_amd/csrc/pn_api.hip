@@ -610,6 +610,79 @@ extern "C" pn_status pn_bench_apply(pn_ctx* c, int iters, int transpose, double*
   return PN_OK;
 }
 
+// Times one kernel of the FP32 Krylov loop with HIP events on the context
+// stream.  The plain applies run `iters` times back to back.  The in-loop
+// kernels run inside `iters` iterations of the loop's own sequence
+// (q = W A p, s -= alpha A^T q, x/p update), so each sees the cache state it
+// sees in a solve; events around the requested kernel give its mean time.
+// The device scalars are reset first (alpha = beta = 0.5, no stop flag); the
+// next solve re-initialises them.
+extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* ms) {
+  if (!c || iters < 1 || !ms || kernel < PN_KERNEL_APPLY || kernel > PN_KERNEL_UPDATE)
+    return c ? fail(c, PN_ERR_ARG, "bad arguments") : PN_ERR_ARG;
+  if (c->use_lds && kernel != PN_KERNEL_APPLY && kernel != PN_KERNEL_APPLY_T)
+    return fail(c, PN_ERR_ARG, "the in-loop kernels are timed on the register-window stencil");
+  DevState init;
+  std::memset(&init, 0, sizeof(init));
+  init.alpha = 0.5;
+  init.beta = 0.5;
+  PN_HIP(hipMemcpyAsync(c->st, &init, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  hipEvent_t e0, e1;
+  PN_HIP(hipEventCreate(&e0));
+  PN_HIP(hipEventCreate(&e1));
+  auto launch = [&](int k) -> hipError_t {
+    StencilArgs a = base_args(c);
+    switch (k) {
+      case PN_KERNEL_APPLY:
+      case PN_KERNEL_APPLY_T:
+        a.tsign = k == PN_KERNEL_APPLY_T ? -1.0 : 1.0;
+        a.x = c->p32; a.y = c->q32;
+        return c->use_lds ? launch_lds(c, M_APPLY, false, a, c->stream)
+                          : launch_stencil<float, M_APPLY, float>(c, a, c->stream);
+      case PN_KERNEL_APPLY_EQ:
+        a.st = c->st; a.partials = c->partials; a.tsign = 1.0;
+        a.x = c->p32; a.y = c->q32;
+        return launch_stencil<float, M_APPLY_EQ, float>(c, a, c->stream);
+      case PN_KERNEL_SUPD:
+        a.st = c->st; a.partials = c->partials; a.tsign = -1.0;
+        a.x = c->q32; a.y = c->s32;
+        return launch_stencil<float, M_SUPD, float>(c, a, c->stream);
+      default:
+        hipLaunchKernelGGL((k_update_xp<float>), dim3(stream_grid(c->nv / 4)), dim3(kBlock), 0, c->stream, c->d32,
+                           c->p32, (const float*)c->s32, (long)c->nv, (const DevState*)c->st);
+        return hipGetLastError();
+    }
+  };
+  double total = 0.0;
+  if (kernel == PN_KERNEL_APPLY || kernel == PN_KERNEL_APPLY_T) {
+    PN_HIP(launch(kernel));  // warm-up
+    PN_HIP(hipEventRecord(e0, c->stream));
+    for (int i = 0; i < iters; ++i) PN_HIP(launch(kernel));
+    PN_HIP(hipEventRecord(e1, c->stream));
+    PN_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    PN_HIP(hipEventElapsedTime(&t, e0, e1));
+    total = t;
+  } else {
+    const int seq[3] = {PN_KERNEL_APPLY_EQ, PN_KERNEL_SUPD, PN_KERNEL_UPDATE};
+    for (int i = 0; i <= iters; ++i) {  // iteration 0 warms up
+      for (int k : seq) {
+        if (k == kernel) PN_HIP(hipEventRecord(e0, c->stream));
+        PN_HIP(launch(k));
+        if (k == kernel) PN_HIP(hipEventRecord(e1, c->stream));
+      }
+      PN_HIP(hipEventSynchronize(e1));
+      float t = 0.f;
+      PN_HIP(hipEventElapsedTime(&t, e0, e1));
+      if (i > 0) total += t;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = total / iters;
+  return PN_OK;
+}
+
 // r = Q - A x in FP64 arithmetic on padded vectors; partials -> st->rtrue2, st->bb2.
 template <typename TO>
 static pn_status residual(pn_ctx* c, const float* rhs_pad, const double* x_pad, TO* r_pad, hipStream_t s) {

@@ -1,6 +1,8 @@
-"""Profiling driver for rocprofv3: runs the in-loop stencil apply of the P5
-128^3 nebula workload a fixed number of times, then a plain 1 GiB device copy
-whose counter readings calibrate FETCH_SIZE / WRITE_SIZE.
+"""Profiling driver for rocprofv3: runs each kernel of the FP32 Krylov loop
+of the P5 128^3 nebula workload (plain apply, equilibrated apply q = W A p,
+s -= alpha A^T q, x/p update) a fixed number of times in its in-loop form,
+then a plain 1 GiB device copy whose counter readings calibrate FETCH_SIZE /
+WRITE_SIZE.
 
     rocprofv3 --pmc FETCH_SIZE -- python3 paper_1807_00410_amd/prof_stencil.py
 """
@@ -18,7 +20,8 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--iters", type=int, default=10)
-    ap.add_argument("--transpose", action="store_true")
+    ap.add_argument("--kernels", default="apply,apply_eq,supd,update",
+                    help="comma-separated: apply, apply_t, apply_eq, supd, update")
     ap.add_argument("--zchunk", type=int, default=2, help="launch z-chunk (the autotuner's choice at P5 128^3)")
     args = ap.parse_args()
     import torch
@@ -28,10 +31,12 @@ def main():
     s = Solver(m.order, m.dims, torch.as_tensor(m.sigma_t).cuda(), torch.as_tensor(m.albedo).cuda(),
                g=m.g, sigma_t_min=m.sigma_t_min)
     s.set_zchunk(args.zchunk)
-    ms = s.bench_apply(args.iters, args.transpose)
     cells = m.dims[0] * m.dims[1] * m.dims[2]
-    print("apply %.4f ms, %.1f GB/s algorithmic (%d unknowns)" % (ms, (8 * s.n + 8 * cells) / ms / 1e6, s.n),
-          flush=True)
+    per_unknown = {"apply": 8, "apply_t": 8, "apply_eq": 8, "supd": 12, "update": 20}
+    for k in args.kernels.split(","):
+        ms = s.bench_kernel(k, args.iters)
+        alg = per_unknown[k] * s.n + (8 * cells if k != "update" else 0)
+        print("%s %.4f ms, %.1f GB/s algorithmic (%d unknowns)" % (k, ms, alg / ms / 1e6, s.n), flush=True)
     a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(3):

@@ -112,6 +112,16 @@ class Solver:
                                            _ptr(r, torch.float64) if r is not None else None, C.byref(rel)))
         return rel.value
 
+    KERNELS = {"apply": 0, "apply_t": 1, "apply_eq": 2, "supd": 3, "update": 4}
+
+    def bench_kernel(self, kernel, iters=20):
+        """Mean milliseconds of one launch of a Krylov-loop kernel in its
+        in-loop form (pn_bench_kernel): "apply", "apply_t", "apply_eq",
+        "supd" or "update"."""
+        ms = C.c_double()
+        self._check(self.lib.pn_bench_kernel(self.ctx, self.KERNELS[kernel], int(iters), C.byref(ms)))
+        return ms.value
+
     def bench_apply(self, iters=20, transpose=False):
         """Mean milliseconds of one in-loop FP32 apply (HIP events)."""
         ms = C.c_double()

@@ -72,6 +72,9 @@ def test_setup_rejects_bad_arguments_on_host(lib):
     # null context calls
     assert lib.pn_apply(None, None, None, 0) == L.PN_ERR_ARG
     assert lib.pn_solve(None, None, None, 1e-8, None, None) == L.PN_ERR_ARG
+    assert lib.pn_row_weights(None, None) == L.PN_ERR_ARG
+    ms = C.c_double()
+    assert lib.pn_bench_kernel(None, 0, 1, C.byref(ms)) == L.PN_ERR_ARG
     lib.pn_destroy(None)
 
 

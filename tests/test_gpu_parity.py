@@ -341,6 +341,31 @@ def test_solve_equilibrated_cg_variant(order, n, bc):
     s.close()
 
 
+def test_bench_kernel_timings_and_state_reset():
+    # every Krylov-loop kernel can be timed in its in-loop form; a solve after
+    # the timings (which overwrite the workspace and the device scalars)
+    # still reaches the oracle's answer
+    from paper_1807_00410_amd.solver import PnError
+    m = config_p3_fbm(n=16, seed=13, order=3)
+    A, lay = oracle_matrix(m)
+    b = rhs_isotropic(lay, m.q00[0])
+    s = make_solver(m)
+    rhs = s.rhs_from_q00(dev(m.q00[0]))
+    s.solve(rhs, tol=1e-8)
+    for k in ("apply", "apply_t", "apply_eq", "supd", "update"):
+        assert s.bench_kernel(k, 3) > 0.0
+    x, info = s.solve(rhs, tol=1e-8)
+    xs = x.cpu().numpy()
+    assert info["status"] == 0 and np.linalg.norm(b - A @ xs) / np.linalg.norm(b) <= 1.01e-8
+    with pytest.raises(PnError):
+        s._check(s.lib.pn_bench_kernel(s.ctx, 7, 3, None))
+    s.set_tiles(32, 4)
+    assert s.bench_kernel("apply", 2) > 0.0
+    with pytest.raises(PnError):
+        s.bench_kernel("supd", 2)
+    s.close()
+
+
 def test_equilibrated_variant_rejects_tiled_stencil_and_fp64():
     from paper_1807_00410_amd.solver import PnError
     m = config_small(3, (12, 10, 9), seed=3)
