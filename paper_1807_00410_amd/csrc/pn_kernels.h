@@ -320,6 +320,15 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
             constexpr int K = decltype(Kc)::value;
             if constexpr (cls_id(K) == c) acc[K] = T(0);
           });
+          // M_SUPD: the class's old outputs are loaded before its differences
+          // are formed, so their latency hides behind that work
+          T yold[NC];
+          if constexpr (MODE == M_SUPD) {
+            sfor<NC>([&](auto Kc) {
+              constexpr int K = decltype(Kc)::value;
+              if constexpr (cls_id(K) == c) yold[K] = T(ldb(Y + cbase(K, zo), oo));
+            });
+          }
           T dcur = T(0);
           sfor<ie - ib>([&](auto Ic) {
             constexpr int I = ib + decltype(Ic)::value;
@@ -361,7 +370,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
                   out = q - out;
                   cn1 = fmadd<T>(q, q, cn1);
                 }
-                if constexpr (MODE == M_SUPD) out = fmadd<T>(-alpha, out, T(ldb(Y + base, oo)));
+                if constexpr (MODE == M_SUPD) out = fmadd<T>(-alpha, out, yold[K]);
                 stb(Y + base, oo, TO(out));
                 if constexpr (NORM && MODE != M_APPLY_EQ && MODE != M_EQS) cn0 = fmadd<T>(out, out, cn0);
                 if constexpr (MODE == M_TRANSR) {
