@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil_lds(const StencilArgs a) {
         sfor<ie - ib>([&](auto Ic) {
           constexpr int I = ib + decltype(Ic)::value;
           constexpr Coupling cp = TB::cpl.v[I];
-          constexpr bool first = (I == ib) || TB::cpl.v[I - 1].kp != cp.kp || TB::cpl.v[I - 1].d != cp.d;
+          constexpr bool first = TB::starts_difference(I);
           if constexpr (first) {
             constexpr int p = cls_axis(cp.kp, cp.d);
             if constexpr (cp.d == 2) {

@@ -190,6 +190,11 @@ struct Table {
   static constexpr int class_begin(int c) { return ranges.b[c]; }
   static constexpr int class_end(int c) { return ranges.b[c + 1]; }
   static constexpr bool class_has_rows(int c) { return ranges.rows[c]; }
+  // coupling i is the first of its (row class, input, axis) run: the place
+  // where that difference is formed
+  static constexpr bool starts_difference(int i) {
+    return i == 0 || cpl.v[i - 1].ck != cpl.v[i].ck || cpl.v[i - 1].kp != cpl.v[i].kp || cpl.v[i - 1].d != cpl.v[i].d;
+  }
 
   static constexpr Need make_need() {
     Need q{};
