@@ -98,7 +98,7 @@ typedef struct {
   double inner_tol;   /* relative reduction of the inner FP32 residual         */
   int use_guess;      /* 0: start from x = 0; 1: start from the x passed in    */
   int graph_iters;    /* Krylov iterations per captured HIP graph launch       */
-  int variant;        /* PN_VARIANT_AUTO, _CGLS or _CG (see below)             */
+  int variant;        /* PN_VARIANT_AUTO, _CGLS, _CG or _CG_EQ (see below)     */
   int learned;        /* PN_LEARNED_* (needs a network, pn_attach_net in pn_nn.h) */
 } pn_solve_opts;
 
@@ -199,9 +199,9 @@ pn_status pn_residual64(pn_ctx* ctx, const float* rhs, const double* x,
 /* Solves A x = Q (rhs = Q, device FP32; x device FP64, in/out) to
  * ||Q - A x||_2 <= tol ||Q||_2 with the residual evaluated in FP64.
  * PN_FP32_IR: iterative refinement around conjugate gradients on the normal
- * equations without forming A^T A (section "Runtime" / "Results"; variant CG
- * by default, CGLS on request) run in FP32 with FP64 dot products and
- * scalars.  PN_FP64: CGLS in FP64 throughout.  Returns PN_ERR_NOT_CONVERGED (x = last iterate, finite) when
+ * equations without forming A^T A (section "Runtime" / "Results"; the
+ * row-equilibrated CG by default, plain CG or CGLS on request) run in FP32
+ * with FP64 dot products and scalars.  PN_FP64: CGLS in FP64 throughout.  Returns PN_ERR_NOT_CONVERGED (x = last iterate, finite) when
  * the limits are hit, PN_ERR_NONFINITE for a non-finite rhs.  rhs == 0
  * returns x = 0 immediately.  opts NULL = defaults; info may be NULL. */
 pn_status pn_solve(pn_ctx* ctx, const float* rhs, double* x, double tol,
@@ -284,8 +284,9 @@ void pn_tune_cache_clear(void);
  * stops on its own.  The right-hand sides of one problem share its A; their
  * thread blocks for one tile run next to each other so the medium is fetched
  * from memory once per tile.  Per system the arithmetic is that of pn_solve
- * (FP32 CGLS, FP64 dot products and iterative refinement) with the same
- * launch shape, so results match pn_solve on the same system bitwise.
+ * (the FP32 Krylov variant of opts, FP64 dot products and iterative
+ * refinement) with the same launch shape, so results match pn_solve on the
+ * same system bitwise.
  * ---------------------------------------------------------------------- */
 typedef struct pn_batch pn_batch;
 
