@@ -159,16 +159,20 @@ def test_autotune_and_cache():
     tune_cache_clear()
 
 
-def test_batch_cgls_variant_matches_single():
-    # the residual-based CGLS form in the batch equals pn_solve's CGLS bitwise
+@pytest.mark.parametrize("variant", ["cgls", "cg", "cg_eq"])
+def test_batch_variants_match_single(variant):
+    # every Krylov variant of the batch equals pn_solve's bitwise
     from paper_1807_00410_amd.solver import Batch
     media = [config_small(5, (7, 6, 8), seed=8, nrhs=2), config_small(3, (9, 7, 6), seed=9, nrhs=2)]
     with Batch(problems(media), 2) as B:
         rhs = [packed_rhs(B.layouts[p], q) for p, m in enumerate(media) for q in m.q00]
-        xs, infos = B.solve(rhs, tol=1e-8, variant="cgls")
+        xs, infos = B.solve(rhs, tol=1e-8, variant=variant)
     for p, m in enumerate(media):
+        A, lay = assemble(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min, bc=m.bc)
         for r in range(2):
             i = p * 2 + r
-            x1, info1, _ = single_solve(m, rhs[i], tol=1e-8, variant="cgls")
+            x1, info1, _ = single_solve(m, rhs[i], tol=1e-8, variant=variant)
             assert infos[i]["status"] == 0 and info1["inner_iters"] == infos[i]["inner_iters"]
             assert torch.equal(x1, xs[i])
+            b = rhs_isotropic(lay, m.q00[r])
+            assert np.linalg.norm(b - A @ xs[i].cpu().numpy()) / np.linalg.norm(b) <= 1.01e-8
