@@ -128,3 +128,33 @@ def test_net_rejects_bad_arguments_on_host(lib):
     assert lib.pn_nn_adam(None, None, None, None, 10, 1, 1e-3, 0.9, 0.999, 1e-8, None) == L.PN_ERR_ARG
     assert lib.pn_nn_last_error()
     lib.pn_net_destroy(None)
+
+
+def test_row_weight_constant_matches_assembled_interior_rows():
+    # The equilibrated variant weights row k by 1 / (d^2 + c_k / h^2), c_k
+    # twice the sum of the squared couplings of row k in the compiled table.
+    # Away from the boundary that is the squared 2-norm of the oracle's
+    # assembled row: check c_k / h^2 = ||row||^2 - d^2 there.
+    import numpy as np
+    from oracle.assemble import assemble
+    from paper_1807_00410_amd.solver import coupling_table
+    rng = np.random.default_rng(4)
+    for order in (1, 2, 3, 5):
+        dims = (6, 5, 7)
+        shp = (dims[2], dims[1], dims[0])
+        st = rng.uniform(1.0, 30.0, shp).astype(np.float32)
+        al = rng.uniform(0.3, 0.95, shp).astype(np.float32)
+        A, lay = assemble(order, dims, st, al, 0.4, 0.5)
+        A = A.tocsr()
+        h = 1.0 / dims[0]
+        ck = {}
+        for k, d, kp, v in coupling_table(order):
+            ck[k] = ck.get(k, 0.0) + 2.0 * v * v
+        rn2 = np.asarray(A.multiply(A).sum(axis=1)).ravel()
+        off2 = rn2 - A.diagonal() ** 2
+        nnz = np.diff(A.indptr)
+        for k in range(len(lay.offset) - 1):
+            sl = slice(lay.offset[k], lay.offset[k + 1])
+            full = nnz[sl] == nnz[sl].max()
+            assert full.any()
+            assert np.allclose(off2[sl][full], ck[k] / h ** 2, rtol=1e-12, atol=0.0)
