@@ -15,11 +15,14 @@ Contents (each function cites the passage of the paper it follows):
                   quadrature; phase-function moments (appendix, phase function)
 * ``closed_form`` the printed closed-form couplings (a..f, beta), with the
                   three corrections stated in that module -- used only as a pin
-* ``stagger``     staggered coefficient classes, extents and vector layout
+* ``stagger``     staggered coefficient classes, extents and vector layout;
+                  boundary types per axis (vacuum/Dirichlet, periodic, Neumann)
 * ``medium``      sigma_t threshold and interpolation of the RTE parameters to
                   the staggered locations
 * ``assemble``    sparse FP64 assembly of A (row by row, SciPy CSR)
-* ``apply``       matrix-free FP64 apply of A / A^T (NumPy), pinned to the CSR
+* ``apply``       matrix-free FP64 apply of A / A^T (NumPy) and ``rows_of``
+                  (single rows from the row equation, for grids too large to
+                  assemble), both pinned to the CSR
 * ``solve``       direct (SuperLU) solve and FP64 CGLS on the normal equations
 
 Every function here is pinned by a ``-m "not gpu"`` test in ``tests/`` except

@@ -5,27 +5,32 @@ differences on the staggered grid), evaluated with whole-array NumPy slices so
 that grids too large for an assembled matrix can be checked.  ``A^T`` is the
 literal transpose: every entry (row, col, v) of A is scattered as (col, row, v).
 It does not use the skew symmetry of the transport part; ``tests/`` checks
-that property separately.
+that property separately.  Boundary rules per axis as in ``assemble``
+(dropped, wrapped, or moved to the closest index inside for Neumann).
 
-``tests/`` pins both functions to the CSR matrix of ``assemble`` on small grids.
+``tests/`` pins both functions, and ``rows_of``, to the CSR matrix of
+``assemble`` on small grids.
 """
 import numpy as np
 
+from .assemble import cell_size
 from .couplings import coupling_list
 from .medium import diagonal
-from .stagger import Layout, BC_PERIODIC
+from .stagger import Layout, BC_PERIODIC, BC_NEUMANN, resolve_index
 
 _AXIS = (2, 1, 0)  # x, y, z -> axis of an (ez, ey, ex) array
 
 
 def _gather(arr, d, offset, out_len, bc):
-    """b[i] = arr[i + offset] along axis d for i < out_len; 0 outside (vacuum)
-    or wrapped (periodic)."""
+    """b[i] = arr[i + offset] along axis d for i < out_len; 0 outside (vacuum),
+    wrapped (periodic) or the closest entry inside (Neumann)."""
     ax = _AXIS[d]
     n = arr.shape[ax]
     idx = np.arange(out_len) + offset
     if bc == BC_PERIODIC:
         return np.take(arr, np.mod(idx, n), axis=ax)
+    if bc == BC_NEUMANN:
+        return np.take(arr, np.clip(idx, 0, n - 1), axis=ax)
     keep = (idx >= 0) & (idx < n)
     shape = list(arr.shape)
     shape[ax] = out_len
@@ -37,12 +42,16 @@ def _gather(arr, d, offset, out_len, bc):
 
 
 def _scatter_add(dst, src, d, offset, bc):
-    """dst[i + offset] += src[i] along axis d (dropped outside unless periodic)."""
+    """dst[i + offset] += src[i] along axis d (dropped outside under the
+    vacuum boundary, wrapped if periodic, clamped inside under Neumann)."""
     ax = _AXIS[d]
     n = dst.shape[ax]
     idx = np.arange(src.shape[ax]) + offset
     if bc == BC_PERIODIC:
         idx = np.mod(idx, n)
+        keep = np.ones(idx.shape, dtype=bool)
+    elif bc == BC_NEUMANN:
+        idx = np.clip(idx, 0, n - 1)
         keep = np.ones(idx.shape, dtype=bool)
     else:
         keep = (idx >= 0) & (idx < n)
@@ -57,12 +66,12 @@ def _scatter_add(dst, src, d, offset, bc):
 class Operator:
     """FP64 matrix-free operator of one medium."""
 
-    def __init__(self, order, dims, sigma_t, albedo, g, sigma_t_min, bc=0, couplings=None):
+    def __init__(self, order, dims, sigma_t, albedo, g, sigma_t_min, bc=0, couplings=None, h=None):
         self.layout = Layout(order, dims, bc)
         self.couplings = coupling_list(order) if couplings is None else couplings
         self.diag = diagonal(self.layout, sigma_t, albedo, g, sigma_t_min)
-        self.h = 1.0 / dims[0]
-        self.bc = bc
+        self.h = cell_size(dims, h)
+        self.bcs = self.layout.bcs
 
     @property
     def n(self):
@@ -78,9 +87,9 @@ class Operator:
             xk = lay.view(x, kp)
             out_len = lay.ext[k][d]
             if lay.cls[kp][d] == 1:
-                plus, minus = _gather(xk, d, 1, out_len, self.bc), _gather(xk, d, 0, out_len, self.bc)
+                plus, minus = _gather(xk, d, 1, out_len, self.bcs[d]), _gather(xk, d, 0, out_len, self.bcs[d])
             else:
-                plus, minus = _gather(xk, d, 0, out_len, self.bc), _gather(xk, d, -1, out_len, self.bc)
+                plus, minus = _gather(xk, d, 0, out_len, self.bcs[d]), _gather(xk, d, -1, out_len, self.bcs[d])
             lay.view(y, k)[...] += (c / self.h) * (plus - minus)
         return y
 
@@ -93,25 +102,28 @@ class Operator:
         for (k, d, kp, c) in self.couplings:
             src = (c / self.h) * lay.view(x, k)
             dst = lay.view(y, kp)
+            b = self.bcs[d]
             if lay.cls[kp][d] == 1:
-                _scatter_add(dst, src, d, 1, self.bc)
-                _scatter_add(dst, -src, d, 0, self.bc)
+                _scatter_add(dst, src, d, 1, b)
+                _scatter_add(dst, -src, d, 0, b)
             else:
-                _scatter_add(dst, src, d, 0, self.bc)
-                _scatter_add(dst, -src, d, -1, self.bc)
+                _scatter_add(dst, src, d, 0, b)
+                _scatter_add(dst, -src, d, -1, b)
         return y
 
 
-def rows_of(order, dims, sigma_t, albedo, g, sigma_t_min, x, rows, bc=0, couplings=None, absolute=False):
+def rows_of(order, dims, sigma_t, albedo, g, sigma_t_min, x, rows, bc=0, couplings=None, absolute=False,
+            h=None):
     """(A x)[row] for the given flat row indices, evaluated one row at a time
     from the row equation (no assembled matrix, no whole-grid arrays).  For
     spot checks of grids too large for ``Operator``.  With ``absolute=True``
-    returns (|A| |x|)[row] instead (the sum of the magnitudes of the terms),
-    the scale of a rounding-error bound."""
+    returns (|A| |x|)[row] instead: every term of the row taken in magnitude,
+    the collision and scattering parts of the diagonal separately
+    (sigma_t + |g|^l sigma_s), the scale of a rounding-error bound."""
     ab = abs if absolute else (lambda v: v)
-    from .stagger import Layout
     from .sh import coeff_lm
     lay = Layout(order, dims, bc)
+    bcs = lay.bcs
     cl = coupling_list(order) if couplings is None else couplings
     by_row = {}
     for (k, d, kp, c) in cl:
@@ -119,7 +131,7 @@ def rows_of(order, dims, sigma_t, albedo, g, sigma_t_min, x, rows, bc=0, couplin
     st = np.maximum(np.asarray(sigma_t, dtype=np.float64), float(np.float32(sigma_t_min)))
     ss = np.asarray(albedo, dtype=np.float64) * st
     n = (dims[0], dims[1], dims[2])
-    h = 1.0 / dims[0]
+    h = cell_size(dims, h)
     g = float(np.float32(g))
     x = np.asarray(x)
     out = np.empty(len(rows))
@@ -133,7 +145,7 @@ def rows_of(order, dims, sigma_t, albedo, g, sigma_t_min, x, rows, bc=0, couplin
         cand = []
         for d in range(3):
             cs = [pt[d]] if p[d] == 0 else [pt[d] - 1, pt[d]]
-            cand.append([(c % n[d]) if bc == BC_PERIODIC else min(max(c, 0), n[d] - 1) for c in cs])
+            cand.append([(c % n[d]) if bcs[d] == BC_PERIODIC else min(max(c, 0), n[d] - 1) for c in cs])
         tsum, ssum, cnt = 0.0, 0.0, 0
         for cz in cand[2]:
             for cy in cand[1]:
@@ -151,9 +163,8 @@ def rows_of(order, dims, sigma_t, albedo, g, sigma_t_min, x, rows, bc=0, couplin
             i = pt[d]
             ip, im = (i + 1, i) if lay.cls[kp][d] == 1 else (i, i - 1)
             for idx, sgn in ((ip, 1.0), (im, -1.0)):
-                if bc == BC_PERIODIC:
-                    idx %= pe[d]
-                elif not (0 <= idx < pe[d]):
+                idx = resolve_index(idx, pe[d], bcs[d])
+                if idx is None:
                     continue
                 q = list(pt)
                 q[d] = idx

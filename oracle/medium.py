@@ -7,7 +7,9 @@
   interpolates them to the row location (section "Precomputation", staggered
   interpolation).  Reading: the arithmetic mean of the 1/2/4/8 cells adjacent
   to the location, cell indices clamped into the domain (vacuum boundary) or
-  wrapped (periodic).  sigma_t and sigma_s are interpolated separately.
+  wrapped (periodic); the Neumann boundary clamps like the vacuum one (the
+  closest cell inside the domain).  sigma_t and sigma_s are interpolated
+  separately.
 * The per-band diagonal (collision minus scattering, appendix "Collision term"
   and "Scattering term"):  sigma_t - sigma_s * lambda_l p^{l,0}, and for a
   Henyey-Greenstein phase function lambda_l p^{l,0} = g^l (pinned in
@@ -19,7 +21,7 @@ rounded once from whatever the caller passes.
 import numpy as np
 
 from .sh import coeff_lm
-from .stagger import BC_PERIODIC
+from .stagger import BC_PERIODIC, bc_axes
 
 
 def threshold(sigma_t, sigma_t_min):
@@ -38,6 +40,7 @@ def interpolate_to_class(field, p, ext, bc):
     f = np.asarray(field, dtype=np.float64)
     nz, ny, nx = f.shape
     n = (nx, ny, nz)
+    bcs = bc_axes(bc)
     idx = []
     for d in range(3):
         i = np.arange(ext[d])
@@ -47,7 +50,7 @@ def interpolate_to_class(field, p, ext, bc):
             cand = [i - 1, i]
         fixed = []
         for c in cand:
-            if bc == BC_PERIODIC:
+            if bcs[d] == BC_PERIODIC:
                 fixed.append(np.mod(c, n[d]))
             else:
                 fixed.append(np.clip(c, 0, n[d] - 1))
@@ -76,8 +79,8 @@ def diagonal(layout, sigma_t, albedo, g, sigma_t_min):
         l, _ = coeff_lm(k)
         p = layout.cls[k]
         if p not in cache:
-            cache[p] = (interpolate_to_class(st, p, layout.ext[k], layout.bc),
-                        interpolate_to_class(ss, p, layout.ext[k], layout.bc))
+            cache[p] = (interpolate_to_class(st, p, layout.ext[k], layout.bcs),
+                        interpolate_to_class(ss, p, layout.ext[k], layout.bcs))
         t, s = cache[p]
         out.append(t - (float(g) ** l) * s)
     return out

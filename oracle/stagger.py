@@ -19,10 +19,18 @@ quadrature couplings rather than assuming it.
 
 Grid: n_x * n_y * n_z cells of size h (unit cube: h = 1/n).  Along axis d a
 coefficient of class p sits at (i + 1/2 - p_d/2) h:
-  * vacuum (homogeneous Dirichlet) boundary: i = 0 .. n_d - 1 + p_d, i.e. the
-    face-centred classes include both boundary faces (the "additional
+  * vacuum (homogeneous Dirichlet) or Neumann boundary: i = 0 .. n_d - 1 + p_d,
+    i.e. the face-centred classes include both boundary faces (the "additional
     coefficients at boundary voxels" of the paper's un-staggering step);
   * periodic boundary: i = 0 .. n_d - 1, indices wrap.
+The boundary type may differ per axis (a 2D problem is a z-periodic grid of
+one cell in z).
+
+Boundary handling of a difference that references an index outside the
+class extent (section "Runtime", last paragraph): the Dirichlet boundary
+drops the entry (the value outside is 0); the Neumann boundary moves the
+entry to the column of the coefficient in the closest location inside the
+domain (the index is clamped into the extent); the periodic grid wraps.
 
 Flat vector layout: coefficients in k order; the array of each coefficient is
 contiguous, z-major / x-fastest over that class's extent.
@@ -33,6 +41,31 @@ from .sh import coeff_lm, num_coeffs
 
 BC_VACUUM = 0
 BC_PERIODIC = 1
+BC_NEUMANN = 2
+
+
+def bc_axes(bc):
+    """Boundary types (x, y, z) from one type for every axis or a 3-sequence."""
+    if isinstance(bc, (int, np.integer)):
+        return (int(bc),) * 3
+    t = tuple(int(b) for b in bc)
+    if len(t) != 3:
+        raise ValueError("bc must be one type or three")
+    return t
+
+
+def resolve_index(idx, ext_d, bc_d):
+    """Index along one axis of an unknown that a difference references: kept
+    when inside [0, ext_d); outside it is dropped (None) under the Dirichlet
+    boundary, wrapped under the periodic one and moved to the closest index
+    inside under the Neumann one."""
+    if 0 <= idx < ext_d:
+        return idx
+    if bc_d == BC_PERIODIC:
+        return idx % ext_d
+    if bc_d == BC_NEUMANN:
+        return min(max(idx, 0), ext_d - 1)
+    return None
 
 
 def coeff_class(l, m):
@@ -51,9 +84,8 @@ def class_of_k(k):
 
 def class_extent(p, dims, bc):
     """(e_x, e_y, e_z) lattice extent of class p on a grid of dims=(nx,ny,nz)."""
-    if bc == BC_PERIODIC:
-        return tuple(int(dims[d]) for d in range(3))
-    return tuple(int(dims[d]) + int(p[d]) for d in range(3))
+    b = bc_axes(bc)
+    return tuple(int(dims[d]) + (0 if b[d] == BC_PERIODIC else int(p[d])) for d in range(3))
 
 
 class Layout:
@@ -62,7 +94,8 @@ class Layout:
     def __init__(self, order, dims, bc=BC_VACUUM):
         self.order = int(order)
         self.dims = tuple(int(v) for v in dims)
-        self.bc = int(bc)
+        self.bcs = bc_axes(bc)
+        self.bc = self.bcs[0] if len(set(self.bcs)) == 1 else self.bcs
         self.ncoeff = num_coeffs(order)
         self.cls = [class_of_k(k) for k in range(self.ncoeff)]
         self.ext = [class_extent(self.cls[k], self.dims, self.bc) for k in range(self.ncoeff)]
