@@ -308,7 +308,10 @@ pn_status pn_batch_setup(int nprob, const pn_problem* probs, int nrhs, int tune,
 pn_status pn_batch_layout(const pn_batch* batch, int prob, pn_layout* layout);
 /* Context of problem `prob` (geometry and medium, no Krylov workspace):
  * valid for pn_layout_query, pn_net_features and pn_net_targets only; owned
- * by the batch.  NULL on bad arguments. */
+ * by the batch.  Every entry point that needs the Krylov workspace (pn_apply,
+ * pn_apply64, pn_row_weights, pn_residual64, pn_solve, the bench and tuning
+ * calls, pn_set_zchunk, pn_set_tiles, pn_attach_net) returns PN_ERR_ARG on it
+ * without touching the device.  NULL on bad arguments. */
 pn_ctx* pn_batch_problem(const pn_batch* batch, int prob);
 /* Launch z-chunk used for problem `prob` (-1 on bad arguments). */
 int pn_batch_zchunk(const pn_batch* batch, int prob);

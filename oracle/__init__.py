@@ -2,9 +2,10 @@
 & Jakob, "P_N-Method for Multiple Scattering in Participating Media", EGSR 2018).
 
 TEST INFRASTRUCTURE ONLY.  This package is the slow, plain, obviously-correct
-reference that the HIP solver is checked against.  Only ``tests/``,
+reference that the HIP solver is checked against.  Only ``tests/``
+(with the reference-solution script ``tests/golden/make_references.py``),
 ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
-import it.  The product path (``paper_1807_00410_amd``) never imports, calls or
+import it (``__graft_entry__.build()`` compiles its C part).  The product path (``paper_1807_00410_amd``) never imports, calls or
 links anything in here, and this package never imports the product path; the
 two share only the seeded input generators in ``synth/``.
 
@@ -24,6 +25,9 @@ Contents (each function cites the passage of the paper it follows):
                   (single rows from the row equation, for grids too large to
                   assemble), both pinned to the CSR
 * ``solve``       direct (SuperLU) solve and FP64 CGLS on the normal equations
+* ``ref``         the same operator (A, A^T) and CGLS in plain C with OpenMP
+                  (``pn_ref.c``, compiled with gcc on first use) for systems too
+                  large for the assembled matrix; pinned to the CSR and SuperLU
 
 Every function here is pinned by a ``-m "not gpu"`` test in ``tests/`` except
 the ones whose docstring says "parity unpinned".

@@ -32,7 +32,27 @@ def _run(cmd, verbose):
         raise RuntimeError("hipcc failed (%d): %s" % (r.returncode, " ".join(cmd[-3:])))
 
 
-def build(verbose=False, jobs=None):
+def _newest_input(path, seen=None):
+    """Newest modification time of a source and of the project headers it
+    includes (quoted #include lines, followed recursively)."""
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return 0.0
+    seen.add(path)
+    t = os.path.getmtime(path)
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("#include") and '"' in line:
+                name = line.split('"')[1]
+                for d in (os.path.dirname(path), os.path.join(ROOT, "include")):
+                    t = max(t, _newest_input(os.path.normpath(os.path.join(d, name)), seen))
+    return t
+
+
+def build(verbose=False, jobs=None, incremental=False):
+    """Compiles every source (incremental=True: only objects older than their
+    source or any header) and links libpn.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(OBJDIR, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include")]
@@ -40,8 +60,10 @@ def build(verbose=False, jobs=None):
     for src in SOURCES:
         obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
         objs.append(obj)
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= _newest_input(os.path.join(HERE, "csrc", src)):
+            continue
         cmds.append([hipcc] + HIPCC_FLAGS + inc + ["-c", os.path.join(HERE, "csrc", src), "-o", obj])
-    jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1), 16)
+    jobs = jobs or max(1, min(len(cmds), os.cpu_count() or 1, 16))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
     tmp = LIB + ".tmp"

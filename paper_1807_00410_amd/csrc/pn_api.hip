@@ -479,6 +479,7 @@ void free_ctx(pn_ctx* c) {
 
 extern "C" pn_status pn_set_zchunk(pn_ctx* c, int zchunk) {
   if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (zchunk < 0) return fail(c, PN_ERR_ARG, "zchunk must be >= 0");
   set_geometry(c, zchunk);
   if (c->nblocks > c->max_blocks) { set_geometry(c, 0); return fail(c, PN_ERR_ARG, "too many blocks"); }
@@ -490,6 +491,7 @@ extern "C" pn_status pn_set_zchunk(pn_ctx* c, int zchunk) {
 
 extern "C" pn_status pn_set_tiles(pn_ctx* c, int tx, int ty, int zchunk) {
   if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
   if (tx == 0 && ty == 0) {  // back to the register-window stencil
     c->use_lds = 0;
@@ -541,6 +543,7 @@ static pn_status ensure64(pn_ctx* c) {
 
 extern "C" pn_status pn_apply(pn_ctx* c, const float* x, float* y, int transpose) {
   if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (!x || !y) return fail(c, PN_ERR_ARG, "x or y is NULL");
   if ((const void*)x == (const void*)y) return fail(c, PN_ERR_ARG, "x and y must not alias");
   // packed -> padded (p32), apply into q32, padded -> packed
@@ -556,6 +559,7 @@ extern "C" pn_status pn_apply(pn_ctx* c, const float* x, float* y, int transpose
 
 extern "C" pn_status pn_row_weights(pn_ctx* c, float* w) {
   if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (!w) return fail(c, PN_ERR_ARG, "w is NULL");
   // W applied to the all-ones vector
   hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, w, (long)c->n, 1.0f);
@@ -570,6 +574,7 @@ extern "C" pn_status pn_row_weights(pn_ctx* c, float* w) {
 
 extern "C" pn_status pn_apply64(pn_ctx* c, const double* x, double* y, int transpose) {
   if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (!x || !y) return fail(c, PN_ERR_ARG, "x or y is NULL");
   if ((const void*)x == (const void*)y) return fail(c, PN_ERR_ARG, "x and y must not alias");
   pn_status e = ensure64(c);
@@ -587,6 +592,7 @@ extern "C" pn_status pn_apply64(pn_ctx* c, const double* x, double* y, int trans
 // of the Krylov loop) with HIP events on the context stream.
 extern "C" pn_status pn_bench_apply(pn_ctx* c, int iters, int transpose, double* ms_per_apply) {
   if (!c || iters < 1 || !ms_per_apply) return c ? fail(c, PN_ERR_ARG, "bad arguments") : PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   hipEvent_t e0, e1;
   PN_HIP(hipEventCreate(&e0));
   PN_HIP(hipEventCreate(&e1));
@@ -620,6 +626,7 @@ extern "C" pn_status pn_bench_apply(pn_ctx* c, int iters, int transpose, double*
 extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* ms) {
   if (!c || iters < 1 || !ms || kernel < PN_KERNEL_APPLY || kernel > PN_KERNEL_UPDATE)
     return c ? fail(c, PN_ERR_ARG, "bad arguments") : PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (c->use_lds && kernel != PN_KERNEL_APPLY && kernel != PN_KERNEL_APPLY_T)
     return fail(c, PN_ERR_ARG, "the in-loop kernels are timed on the register-window stencil");
   DevState init;
@@ -697,6 +704,7 @@ static pn_status residual(pn_ctx* c, const float* rhs_pad, const double* x_pad, 
 
 extern "C" pn_status pn_residual64(pn_ctx* c, const float* rhs, const double* x, double* r, double* rel) {
   if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (!rhs || !x) return fail(c, PN_ERR_ARG, "rhs or x is NULL");
   pn_status s = ensure64(c);
   if (s != PN_OK) return s;
@@ -899,6 +907,7 @@ static pn_status net_scale(pn_ctx* c, const float* rhs_pad, hipStream_t s, doubl
 
 extern "C" pn_status pn_attach_net(pn_ctx* c, pn_net* net) {
   if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   c->net = net;
   return PN_OK;
 }
@@ -1090,6 +1099,7 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
 extern "C" pn_status pn_solve(pn_ctx* c, const float* rhs, double* x, double tol, const pn_solve_opts* opts,
                               pn_solve_info* info) {
   if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (!rhs || !x) return fail(c, PN_ERR_ARG, "rhs or x is NULL");
   if (!(tol > 0.0)) return fail(c, PN_ERR_ARG, "tol must be > 0");
   pn_solve_opts o;

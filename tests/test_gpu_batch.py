@@ -176,3 +176,38 @@ def test_batch_variants_match_single(variant):
             assert torch.equal(x1, xs[i])
             b = rhs_isotropic(lay, m.q00[r])
             assert np.linalg.norm(b - A @ xs[i].cpu().numpy()) / np.linalg.norm(b) <= 1.01e-8
+
+
+def test_batch_problem_context_refuses_workspace_calls():
+    """A batch problem's context has no Krylov workspace: every entry point
+    that would need it returns PN_ERR_ARG on the host, launching nothing."""
+    import ctypes as C
+    from paper_1807_00410_amd import _lib as L
+    from paper_1807_00410_amd.solver import Batch
+    m = config_small(3, (5, 4, 3), seed=4)
+    lib = L.load()
+    with Batch(problems([m]), 1) as B:
+        ctx = lib.pn_batch_problem(B.b, 0)
+        assert ctx
+        n = B.layouts[0].n
+        x = torch.zeros(n, dtype=torch.float32, device="cuda")
+        y = torch.zeros(n, dtype=torch.float32, device="cuda")
+        x64 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        y64 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        p = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+        ms = C.c_double()
+        rel = C.c_double()
+        calls = [
+            lib.pn_apply(ctx, p(x), p(y), 0),
+            lib.pn_row_weights(ctx, p(y)),
+            lib.pn_apply64(ctx, p(x64), p(y64), 1),
+            lib.pn_residual64(ctx, p(x), p(x64), p(y64), C.byref(rel)),
+            lib.pn_solve(ctx, p(x), p(x64), C.c_double(1e-8), None, None),
+            lib.pn_bench_apply(ctx, 1, 0, C.byref(ms)),
+            lib.pn_bench_kernel(ctx, 0, 1, C.byref(ms)),
+            lib.pn_set_zchunk(ctx, 2),
+            lib.pn_set_tiles(ctx, 32, 4, 0),
+        ]
+        assert calls == [L.PN_ERR_ARG] * len(calls)
+        assert b"no Krylov workspace" in lib.pn_last_error(ctx)
+        torch.cuda.synchronize()
