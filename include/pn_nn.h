@@ -46,6 +46,18 @@ pn_status pn_nn_conv3d_dgrad(int B, int nx, int ny, int nz, const uint16_t* g, c
  * workspace; synchronous. */
 pn_status pn_nn_conv3d_wgrad(int B, int nx, int ny, int nz, const uint16_t* x, const uint16_t* g,
                              float* dw, float* db, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the weight
+ * gradient of pn_nn_conv3d_wgrad with the same arguments, results and
+ * kernels, whose per-block partial sums live in a static device array of
+ * 128 x (27*32*32 + 32) floats (14.2 MB, held by every device the library
+ * runs on until the process ends) instead of a temporary allocation.
+ * Allocates nothing.  Asynchronous on `stream`.  Volumes needing more than
+ * 128 partial blocks (B*nx*ny*nz > 32768) fail with PN_ERR_ARG.  All calls on
+ * one device share its array: calls that overlap on one device (different
+ * streams, or host threads) race and must be serialised by the caller. */
+pn_status pn_nn_conv3d_wgrad_noalloc(int B, int nx, int ny, int nz, const uint16_t* x, const uint16_t* g,
+                                     float* dw, float* db, void* stream);
 /* 2x2x2 average pooling of x (extents nx, ny, nz even) into y (half extents). */
 pn_status pn_nn_pool2(int B, int nx, int ny, int nz, const uint16_t* x, uint16_t* y, void* stream);
 /* gf = adjoint of pool2 applied to gc (half extents) + skip (NULL: none). */

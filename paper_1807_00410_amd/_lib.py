@@ -102,6 +102,7 @@ NN_SIGNATURES = [
     ("pn_nn_conv3d", _I, [_I, _I, _I, _I, _V, _V, _V, _I, _I, _V, _V]),
     ("pn_nn_conv3d_dgrad", _I, [_I, _I, _I, _I, _V, _V, _V, _V]),
     ("pn_nn_conv3d_wgrad", _I, [_I, _I, _I, _I, _V, _V, _V, _V, _V]),
+    ("pn_nn_conv3d_wgrad_noalloc", _I, [_I, _I, _I, _I, _V, _V, _V, _V, _V]),
     ("pn_nn_pool2", _I, [_I, _I, _I, _I, _V, _V, _V]),
     ("pn_nn_pool2_bwd_add", _I, [_I, _I, _I, _I, _V, _V, _V, _V]),
     ("pn_nn_up2_add", _I, [_I, _I, _I, _I, _V, _V, _V, _V]),

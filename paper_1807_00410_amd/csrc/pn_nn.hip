@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -503,6 +504,61 @@ extern "C" pn_status pn_nn_conv3d_wgrad(int B, int nx, int ny, int nz, const uin
   hipFree(wp);
   hipFree(bp);
   NN_HIP(e);
+  return PN_OK;
+}
+
+// ------------------------------------------- allocation-free weight gradient --
+// The per-block partial sums of the weight gradient live in a file-scope
+// device array instead of a temporary allocation.  Each device holds its own
+// copy; its address is taken once per device with hipGetSymbolAddress (the
+// array's name in host code is not a device address).  Every call on a device
+// shares that device's copy: calls that overlap on one device race.
+namespace {
+constexpr int kWgradScratchBlocks = 128;
+constexpr long long kWgradScratchFloats = (long long)kWgradScratchBlocks * (kWElems + kC);
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) float scratch[kWgradScratchFloats];
+
+static float* g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch array (taken on first use).
+static hipError_t scratch_address(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+extern "C" pn_status pn_nn_conv3d_wgrad_noalloc(int B, int nx, int ny, int nz, const uint16_t* x,
+                                                const uint16_t* g, float* dw, float* db, void* stream) {
+  if (!dims_ok(B, nx, ny, nz) || !x || !g || !dw || !db) return nfail(nullptr, PN_ERR_ARG, "bad arguments");
+  const Dims d = mk(B, nx, ny, nz);
+  int nblk;
+  long long per;
+  wgrad_split(d, &nblk, &per);
+  if (nblk > kWgradScratchBlocks)
+    return nfail(nullptr, PN_ERR_ARG,
+                 "volume of " + std::to_string(d.V) + " voxels needs " + std::to_string(nblk) +
+                     " partial-sum blocks; the allocation-free weight gradient holds at most " +
+                     std::to_string(kWgradScratchBlocks) + " (B*nx*ny*nz <= " +
+                     std::to_string(kWgradScratchBlocks * 256) + ")");
+  float* sp = nullptr;
+  NN_HIP(scratch_address(&sp));
+  // every partial of blocks [0, nblk) is written by the weight-gradient
+  // kernel before the reduction reads it: nothing to clear
+  NN_HIP(conv_wgrad(d, x, g, dw, db, sp, sp + (long long)kWgradScratchBlocks * kWElems, (hipStream_t)stream));
   return PN_OK;
 }
 

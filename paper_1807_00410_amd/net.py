@@ -71,6 +71,17 @@ def conv3d_wgrad(x, g, stream=None):
     return dw, db
 
 
+def conv3d_wgrad_noalloc(x, g, dw, db, stream=None):
+    """Weight gradient into caller-provided dw (FP32 [27, 32, 32]) and db
+    (FP32 [32]) through the allocation-free entry point (asynchronous)."""
+    B, nx, ny, nz = _dims(x)
+    if dw.shape != (27, KC, KC) or db.shape != (KC,):
+        raise ValueError("dw must be [27, 32, 32] and db [32]")
+    _chk(L.load().pn_nn_conv3d_wgrad_noalloc(B, nx, ny, nz, _p(x, torch.bfloat16), _p(g, torch.bfloat16),
+                                             _p(dw, torch.float32), _p(db, torch.float32), _s(stream)))
+    return dw, db
+
+
 def pool2(x, stream=None):
     B, nx, ny, nz = _dims(x)
     y = torch.empty((B, nz // 2, ny // 2, nx // 2, KC), dtype=torch.bfloat16, device=x.device)
