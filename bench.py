@@ -7,17 +7,25 @@ residual), inputs resident in HBM.  Prints one JSON line.
 
 Also reported (JSON keys):
   roofline      the kernel of the Krylov loop that takes the most time per
-                iteration (s -= alpha A^T q at P5 128^3), timed in its in-loop
-                form with HIP events on the stream it runs on: algorithmic
-                bytes per launch / mean launch time, against the 8 TB/s HBM
-                peak; traffic = HBM bytes per launch from the committed
-                rocprofv3 FETCH_SIZE / WRITE_SIZE summary when it was taken
-                on the current kernel sources.
+                iteration, timed in its in-loop form with HIP events on the
+                stream it runs on: algorithmic bytes per launch / mean launch
+                time, against the 8 TB/s HBM peak; traffic = HBM bytes per
+                launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+                summary when it was taken on the current kernel sources.
   loop_kernels  the same figures for every kernel of the loop (the plain
                 apply, q = W A p, s -= alpha A^T q, the x/p update).
-  cpu_baseline  the FP64 oracle (NumPy, one thread) timed for one CGLS
-                iteration at the full size, scaled by the GPU solve's
-                iteration count.
+  cpu_baseline  the C/OpenMP FP64 oracle's CGLS (oracle/pn_ref.c) timed for a
+                bounded number of iterations on the full P5 128^3 system on
+                this host's cores, scaled by the iterations the oracle's CGLS
+                needs to reach 1e-8 on it (its full run, profiles/).
+  accuracy      relative L2 error of the GPU solution against the oracle's
+                FP64 solution to 1e-12 (when the reference file is present)
+                and the oracle's residual of the GPU solution.
+  configs       the other workloads: P1 16^3 (FP64 Krylov to 1e-10, error vs
+                SuperLU), P3 64^3 (error vs the committed oracle reference),
+                P5 128^3 with g = 0.5, the batched workload (48 media x 8
+                right-hand sides) and the held-out P3 96^3 medium, plain vs
+                learned.
 """
 import argparse
 import hashlib
@@ -65,37 +73,156 @@ LOOP_KERNELS = (
 )
 
 
-def cpu_baseline(medium, gpu_iters):
-    """One FP64 CGLS iteration of the oracle at the full size (A p, A^T r and
-    the vector updates), scaled by the number of iterations the GPU solve
-    took.  NumPy element-wise work runs on one thread."""
+def oracle_run(tag):
+    """Summary of the oracle's full reference run of a workload (profiles/)."""
+    path = os.path.join(ROOT, "profiles", "oracle_%s.json" % tag)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def cpu_baseline(medium, iters):
+    """The C/OpenMP FP64 oracle's CGLS (A p, A^T r and the vector updates of
+    oracle/pn_ref.c) on the full system for `iters` iterations on this host's
+    cores, scaled by the iterations the oracle's own CGLS takes to reach 1e-8
+    on this workload (its full run to 1e-12, profiles/oracle_p5_128_g0.json)."""
     import numpy as np
-    from oracle.apply import Operator
-    op = Operator(medium.order, medium.dims, medium.sigma_t, medium.albedo, medium.g, medium.sigma_t_min)
-    rng = np.random.default_rng(0)
-    p = rng.normal(size=op.n)
-    r = rng.normal(size=op.n)
-    x = np.zeros(op.n)
-    t0 = time.perf_counter()
-    q = op.matvec(p)
-    alpha = float(r @ r) / float(q @ q)
-    x += alpha * p
-    r -= alpha * q
-    s = op.rmatvec(r)
-    gamma = float(s @ s)
-    p = s + (gamma / (gamma + 1.0)) * p
-    t_iter = time.perf_counter() - t0
-    return {"value": t_iter * gpu_iters, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": "one FP64 CGLS iteration (A p, A^T r, vector updates) of the NumPy oracle on the full "
-                      "P5 128^3 system (%.1f s), scaled by the %d iterations of the GPU solve" % (t_iter, gpu_iters),
-            "seconds_per_iteration": t_iter}
+    from oracle.assemble import rhs_isotropic
+    from oracle.ref import CRef
+    R = CRef(medium.order, medium.dims, medium.sigma_t, medium.albedo, medium.g, medium.sigma_t_min)
+    b = rhs_isotropic(R.layout, medium.q00[0])
+    _, info = R.cgls(b, tol=0.0, max_iter=iters)
+    per_it = info["seconds"] / max(info["iters"], 1)
+    full = oracle_run("p5_128_g%g" % medium.g)
+    n8 = full["iters_to"]["1e-08"] if full else None
+    out = {"value": per_it * n8 if n8 else None, "unit": "s", "cores": info["threads"], "kind": "oracle",
+           "sample": "%d FP64 CGLS iterations of the C/OpenMP oracle on the full P5 128^3 system (%.1f s, %d threads), "
+                     "scaled by the %s iterations the oracle's CGLS takes to 1e-8 on it"
+                     % (info["iters"], info["seconds"], info["threads"], n8),
+           "seconds_per_iteration": per_it, "oracle_iters_to_1e-8": n8}
+    if full:
+        out["full_run"] = {k: full.get(k) for k in ("iters", "tol", "rel_residual", "seconds", "threads", "cpu", "date",
+                                                    "command")}
+    return out, R
 
 
-def bench_batch(args):
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def reference_error(x, tag):
+    """rel-L2 error of a GPU solution against the oracle's stored FP64 (1e-12)
+    solution, when that file is present (refdata/, not in the repository)."""
+    import numpy as np
+    path = os.path.join(ROOT, "refdata", "ref_%s.npy" % tag)
+    if not os.path.exists(path):
+        return None
+    return rel_l2(x, np.load(path).astype(np.float64))
+
+
+def timed_solve(s, rhs, x, warmup=1, **kw):
+    import torch
+    for _ in range(warmup):
+        s.solve(rhs, x=x, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, info = s.solve(rhs, x=x, **kw)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, info
+
+
+def extra_configs(args):
+    """The workloads beside the headline one, each with its time, iterations
+    and accuracy against the oracle."""
+    import numpy as np
+    import torch
+    from oracle.assemble import assemble, rhs_isotropic
+    from oracle.solve import direct
+    from synth import config_p1_homogeneous, config_p3_fbm, config_p5_nebula
+    from paper_1807_00410_amd.solver import Solver
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def mk(m):
+        return Solver(m.order, m.dims, torch.as_tensor(m.sigma_t).to(dev), torch.as_tensor(m.albedo).to(dev), g=m.g,
+                      sigma_t_min=m.sigma_t_min)
+
+    # P1 16^3 homogeneous: FP64 Krylov to 1e-10, error against SuperLU
+    m = config_p1_homogeneous(16)
+    s = mk(m)
+    rhs = s.rhs_from_q00(torch.as_tensor(m.q00[0]).to(dev))
+    x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+    sec, info = timed_solve(s, rhs, x, tol=1e-10, precision="fp64")
+    A, lay = assemble(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min)
+    u = direct(A, rhs_isotropic(lay, m.q00[0]))
+    out["p1_16"] = {"workload": "P1 16^3 homogeneous (sigma_t 10, albedo 0.9), FP64 CGLS to 1e-10",
+                    "seconds": sec, "iters": info["inner_iters"], "rel_residual": info["rel_residual"],
+                    "rel_l2_vs_oracle": rel_l2(x.cpu().numpy(), u), "oracle": "SuperLU"}
+    s.close()
+    print("[bench] P1 16^3: %.4fs iters %d err %.2e" % (sec, info["inner_iters"], out["p1_16"]["rel_l2_vs_oracle"]),
+          file=sys.stderr, flush=True)
+    # P3 64^3 fBm: error against the committed oracle reference (CGLS to 1e-12)
+    m = config_p3_fbm(n=64, seed=1)
+    s = mk(m)
+    rhs = s.rhs_from_q00(torch.as_tensor(m.q00[0]).to(dev))
+    x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+    sec, info = timed_solve(s, rhs, x, tol=args.tol, inner_tol=args.inner_tol)
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "ref_p3_64.npz"))["u"].astype(np.float64)
+    out["p3_64"] = {"workload": "P3 64^3 fBm (sigma_t 50 fBm, albedo U[0.8,0.99], g 0.3, Gaussian blob), to %g"
+                                % args.tol, "seconds": sec, "iters": info["inner_iters"],
+                    "rel_residual": info["rel_residual"], "rel_l2_vs_oracle": rel_l2(x.cpu().numpy(), ref),
+                    "oracle": "oracle CGLS to 1e-12 (tests/golden/ref_p3_64.npz)"}
+    s.close()
+    print("[bench] P3 64^3: %.3fs iters %d err %.2e" % (sec, info["inner_iters"], out["p3_64"]["rel_l2_vs_oracle"]),
+          file=sys.stderr, flush=True)
+    # P5 128^3 nebula, g = 0.5
+    m = config_p5_nebula(n=args.n, seed=3, g=0.5, order=args.order)
+    s = mk(m)
+    s.autotune(10)
+    rhs = s.rhs_from_q00(torch.as_tensor(m.q00[0]).to(dev))
+    x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+    sec, info = timed_solve(s, rhs, x, tol=args.tol, inner_tol=args.inner_tol)
+    xs = x.cpu().numpy()
+    out["p5_128_g0.5"] = {"workload": "P5 128^3 nebula, g 0.5, to %g" % args.tol, "seconds": sec,
+                          "iters": info["inner_iters"], "outer_iters": info["outer_iters"],
+                          "rel_residual": info["rel_residual"], "rel_l2_vs_oracle": reference_error(xs, "p5_128_g0.5")}
+    s.close()
+    print("[bench] P5 128^3 g=0.5: %.3fs iters %d" % (sec, info["inner_iters"]), file=sys.stderr, flush=True)
+    # held-out P3 96^3 medium: plain vs learned
+    if os.path.exists(args.weights):
+        from paper_1807_00410_amd.net import Net
+        m = config_p3_fbm(n=96, seed=90002, order=3)
+        s = mk(m)
+        rhs = s.rhs_from_q00(torch.as_tensor(m.q00[0]).to(dev))
+        x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+        sec, info = timed_solve(s, rhs, x, tol=args.tol, inner_tol=args.inner_tol)
+        r = {"workload": "P3 96^3 fBm, held-out seed 90002, to %g" % args.tol,
+             "plain": {"seconds": sec, "iters": info["inner_iters"]}}
+        net = Net(seed=0)
+        net.load(args.weights)
+        s.attach_net(net)
+        for mode in ("guess", "guess+correct"):
+            sl, li = timed_solve(s, rhs, x, tol=args.tol, inner_tol=args.inner_tol, learned=mode)
+            r[mode] = {"seconds": sl, "iters": li["inner_iters"], "learned_steps": li["learned_steps"],
+                       "guess_residual_ratio": li["learned_ratio"], "speedup_vs_plain": sec / sl}
+        s.attach_net(None)
+        net.close()
+        s.close()
+        out["p3_96_heldout"] = r
+        print("[bench] P3 96^3 held-out: plain %.3fs, guess %.3fs" % (sec, r["guess"]["seconds"]), file=sys.stderr,
+              flush=True)
+    # the batched workload
+    out["batch"] = bench_batch(args, quiet=True)
+    return out
+
+
+def bench_batch(args, quiet=False):
     """The batched workload: 48 seeded media (n in {32,48,64,96}, orders
     P1/P3/P5/P7, fBm sigma_t in [0,100], albedo 0.9, g = 0), 8 Gaussian
     emission fields each, solved together to tol with autotuned launch shapes.
-    Prints one JSON line."""
+    Prints one JSON line (returns the dict instead when quiet)."""
     import numpy as np
     import torch
     from synth import config_batch
@@ -147,7 +274,37 @@ def bench_batch(args):
         "zchunks": [B.zchunk(p) for p in range(len(media))],
     }
     B.close()
+    if quiet:
+        return out
     print(json.dumps(out), flush=True)
+
+
+def profile_kernels(args):
+    """Profiling mode for rocprofv3 (--profile-kernels): runs each kernel of
+    the FP32 Krylov loop of the P5 nebula workload (plain apply, q = W A p,
+    s -= alpha A^T q, x/p update) `--profile-iters` times in its in-loop form
+    at a fixed z-chunk, then three plain 1 GiB device copies whose counter
+    readings calibrate FETCH_SIZE / WRITE_SIZE (bytes per copy known).  Prints
+    the live timings; the counters come from the profiler."""
+    import torch
+    from synth import config_p5_nebula
+    from paper_1807_00410_amd.solver import Solver
+    m = config_p5_nebula(n=args.n, order=args.order, g=args.g)
+    s = Solver(m.order, m.dims, torch.as_tensor(m.sigma_t).cuda(), torch.as_tensor(m.albedo).cuda(),
+               g=m.g, sigma_t_min=m.sigma_t_min)
+    s.set_zchunk(args.profile_zchunk)
+    cells = m.dims[0] * m.dims[1] * m.dims[2]
+    per_unknown = {"apply": 8, "apply_t": 8, "apply_eq": 8, "supd": 12, "update": 20}
+    for k in args.profile_kernels.split(","):
+        ms = s.bench_kernel(k, args.profile_iters)
+        alg = per_unknown[k] * s.n + (8 * cells if k != "update" else 0)
+        print("%s %.4f ms, %.1f GB/s algorithmic (%d unknowns)" % (k, ms, alg / ms / 1e6, s.n), flush=True)
+    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)  # calibration: 1 GiB read + 1 GiB written per copy
+    torch.cuda.synchronize()
+    s.close()
 
 
 def main():
@@ -162,16 +319,27 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-2)
     ap.add_argument("--apply-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CGLS iterations timed for the CPU baseline")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads (P1, P3 64^3, P5 g=0.5, "
+                                                             "batch, P3 96^3 held-out)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the pure FP64 Krylov comparison solve")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned + mixed-precision solve")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1807_00410_amd", "weights", "unet_p3.bin"))
     ap.add_argument("--workload", choices=("p5", "batch"), default="p5")
     ap.add_argument("--batch-media", type=int, default=48)
+    ap.add_argument("--profile-kernels", default=None, metavar="LIST",
+                    help="profiling mode: comma-separated loop kernels (apply, apply_t, apply_eq, supd, update) "
+                         "run in their in-loop form for rocprofv3, then the counter-calibration copies")
+    ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--profile-zchunk", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.profile_kernels:
+        profile_kernels(args)
+        return
     if args.workload == "batch":
         bench_batch(args)
         return
@@ -217,6 +385,7 @@ def main():
               file=sys.stderr, flush=True)
     total = time.perf_counter() - t_all
     sec = sum(times) / len(times)
+    xs = x.cpu().numpy()  # the solution of the last timed step
 
     # Krylov-loop kernels in their in-loop form (HIP events on their stream)
     ms_apply = s.bench_apply(args.apply_iters, transpose=False)
@@ -318,17 +487,20 @@ def main():
                      "ms_per_launch": loop[dom]["ms"], "kernel": loop[dom]["kernel"], "source_hash": khash},
         "loop_kernels": loop,
     }
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle, ~20-30 s)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(m, infos[-1]["inner_iters"])
-        # the FP64 oracle's own residual of the GPU solution (one CPU matvec)
-        from oracle.apply import Operator
-        xs = x.cpu().numpy()
-        op = Operator(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min)
-        b = np.zeros(op.n)
-        b[:m.dims[0] * m.dims[1] * m.dims[2]] = m.q00[0].astype(np.float64).reshape(-1)
-        out["oracle_rel_residual"] = float(np.linalg.norm(b - op.matvec(xs)) / np.linalg.norm(b))
     s.close()
+    out["accuracy"] = {"rel_l2_vs_oracle": reference_error(xs, "p5_128_g%g" % m.g),
+                       "oracle": "oracle CGLS (C, FP64) to 1e-12 from u = 0; refdata/ref_p5_128_g%g.npy "
+                                 "(not in the repository: null when absent; its figure is in profiles/)" % m.g}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (C oracle, %d CGLS iterations)" % args.cpu_iters, file=sys.stderr, flush=True)
+        from oracle.assemble import rhs_isotropic
+        out["cpu_baseline"], R = cpu_baseline(m, args.cpu_iters)
+        # the FP64 oracle's own residual of the GPU solution (one CPU matvec)
+        b = rhs_isotropic(R.layout, m.q00[0])
+        out["accuracy"]["oracle_rel_residual"] = float(np.linalg.norm(b - R.matvec(xs)) / np.linalg.norm(b))
+        del R
+    if not args.no_configs:
+        out["configs"] = extra_configs(args)
     print(json.dumps(out), flush=True)
 
 

@@ -54,17 +54,24 @@ typedef enum {
   PN_ERR_BREAKDOWN = 6       /* Krylov breakdown (zero curvature)             */
 } pn_status;
 
-typedef enum { PN_BC_VACUUM = 0, PN_BC_PERIODIC = 1 } pn_bc;
+typedef enum { PN_BC_VACUUM = 0, PN_BC_PERIODIC = 1, PN_BC_NEUMANN = 2, PN_BC_PER_AXIS = 3 } pn_bc;
 typedef enum { PN_FP32_IR = 0, PN_FP64 = 1 } pn_precision;
 
 /* Grid of nx*ny*nz cells of edge h (h <= 0 selects h = 1/nx, i.e. the unit
- * cube for cubic grids).  bc: PN_BC_VACUUM = homogeneous Dirichlet on every
- * coefficient (the paper's Dirichlet mode: writes to locations outside the
- * domain are dropped, section "Runtime"), PN_BC_PERIODIC = wrap-around. */
+ * cube for cubic grids).  bc, the same on every axis: PN_BC_VACUUM =
+ * homogeneous Dirichlet on every coefficient (the paper's Dirichlet mode:
+ * entries referencing a location outside the domain are dropped, section
+ * "Runtime"), PN_BC_PERIODIC = wrap-around, PN_BC_NEUMANN = the paper's
+ * Neumann mode (such an entry moves to the coefficient at the closest
+ * location inside the domain, section "Runtime"); PN_BC_PER_AXIS: the type
+ * of axis d is bc_axis[d] (one of the three; e.g. a 2D problem as one
+ * periodic cell in z).  Face-centred classes have n_d + 1 points along a
+ * vacuum or Neumann axis, n_d along a periodic one. */
 typedef struct {
   int nx, ny, nz;
   double h;
   int bc;
+  int bc_axis[3];     /* used when bc == PN_BC_PER_AXIS */
 } pn_grid;
 
 /* RTE parameters at the cell centres (section "Runtime": "RTE parameter
@@ -85,6 +92,7 @@ typedef struct {
 typedef struct {
   int order, ncoeff;
   int nx, ny, nz, bc;
+  int bc_axis[3];                    /* boundary type of each axis           */
   long long n_unknowns;
   int cls[PN_MAX_COEFF][3];
   int ext[PN_MAX_COEFF][3];          /* (ex, ey, ez) per coefficient          */
@@ -135,6 +143,18 @@ typedef struct {
 #define PN_VARIANT_CG_EQ 3
 
 #define PN_MAX_HISTORY 64
+/* Phases of a solve timed in pn_solve_info.t_ms (wall milliseconds, host
+ * clock at the points where the solve synchronises with the device):
+ * SETUP: argument checks, the non-finite check of Q, packing Q and x0;
+ * RESIDUAL: the FP64 residual evaluations of the refinement; KRYLOV: the FP32
+ * (or FP64) inner Krylov solves; LEARNED: network predictions and their
+ * residual-minimising scaling; FINISH: unpacking x. */
+#define PN_PHASES 5
+#define PN_PHASE_SETUP 0
+#define PN_PHASE_RESIDUAL 1
+#define PN_PHASE_KRYLOV 2
+#define PN_PHASE_LEARNED 3
+#define PN_PHASE_FINISH 4
 typedef struct {
   int status;
   int outer_iters;          /* FP64 residual evaluations                       */
@@ -146,6 +166,14 @@ typedef struct {
   double history[PN_MAX_HISTORY]; /* FP64 relative residual per refinement step */
   int learned_steps;        /* learned guesses / corrections applied           */
   double learned_ratio;     /* residual ratio the learned initial guess offers  */
+  double t_ms[PN_PHASES];   /* wall milliseconds per phase (PN_PHASE_*); zero in
+                               the per-system infos of pn_batch_solve           */
+  double bytes;             /* algorithmic memory traffic of the solve's kernels:
+                               vector elements each kernel must read and write
+                               (per unknown) and the medium (8 bytes per cell
+                               per stencil pass) -- not a counter reading       */
+  double achieved_gbs;      /* bytes / (RESIDUAL + KRYLOV time), GB/s; zero in
+                               the per-system infos of pn_batch_solve           */
 } pn_solve_info;
 
 int pn_abi_version(void);
@@ -266,7 +294,8 @@ int pn_coupling_table(int order, int* k, int* d, int* kp, double* v, int cap);
 pn_status pn_autotune(pn_ctx* ctx, int iters, int* zchunk, double* ms_per_apply);
 
 /* The tune cache as a text file, one entry per line:
- * "order nx ny nz bc zchunk ms" ('#' starts a comment line).  Load merges the
+ * "order nx ny nz bc zchunk ms" ('#' starts a comment line), bc = the
+ * boundary types of the axes as bc_x + 3 bc_y + 9 bc_z (0..26).  Load merges the
  * file into the cache (PN_ERR_ARG on a missing file or a malformed line; the
  * lines before it are kept). */
 pn_status pn_tune_cache_save(const char* path);

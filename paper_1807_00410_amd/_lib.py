@@ -7,6 +7,8 @@ LIB_PATH = os.path.join(HERE, "libpn.so")
 
 PN_MAX_COEFF = 64
 PN_MAX_HISTORY = 64
+PN_PHASES = 5
+PHASES = ("setup", "residual", "krylov", "learned", "finish")
 
 PN_OK = 0
 PN_ERR_ARG = 1
@@ -18,12 +20,15 @@ PN_ERR_BREAKDOWN = 6
 
 PN_BC_VACUUM = 0
 PN_BC_PERIODIC = 1
+PN_BC_NEUMANN = 2
+PN_BC_PER_AXIS = 3
 PN_FP32_IR = 0
 PN_FP64 = 1
 
 
 class PnGrid(C.Structure):
-    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double), ("bc", C.c_int)]
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double), ("bc", C.c_int),
+                ("bc_axis", C.c_int * 3)]
 
 
 class PnMedium(C.Structure):
@@ -32,7 +37,7 @@ class PnMedium(C.Structure):
 
 class PnLayout(C.Structure):
     _fields_ = [("order", C.c_int), ("ncoeff", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
-                ("bc", C.c_int), ("n_unknowns", C.c_longlong),
+                ("bc", C.c_int), ("bc_axis", C.c_int * 3), ("n_unknowns", C.c_longlong),
                 ("cls", (C.c_int * 3) * PN_MAX_COEFF), ("ext", (C.c_int * 3) * PN_MAX_COEFF),
                 ("offset", C.c_longlong * (PN_MAX_COEFF + 1))]
 
@@ -47,7 +52,8 @@ class PnSolveInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("outer_iters", C.c_int), ("inner_iters", C.c_int),
                 ("rel_residual", C.c_double), ("bnorm", C.c_double), ("seconds", C.c_double),
                 ("nhistory", C.c_int), ("history", C.c_double * PN_MAX_HISTORY),
-                ("learned_steps", C.c_int), ("learned_ratio", C.c_double)]
+                ("learned_steps", C.c_int), ("learned_ratio", C.c_double),
+                ("t_ms", C.c_double * PN_PHASES), ("bytes", C.c_double), ("achieved_gbs", C.c_double)]
 
 
 class PnProblem(C.Structure):

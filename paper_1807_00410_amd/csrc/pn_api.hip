@@ -28,7 +28,7 @@ static constexpr size_t kLdsMax = 160 * 1024;
 
 // Tile geometry of the LDS kernel; returns false if the shape is not usable.
 static bool set_tiles(pn_ctx* c, int TX, int TY, int zchunk) {
-  if (c->bc != PN_BC_VACUUM || TX < 1 || TY < 1) return false;
+  if (c->bcs[0] != BC_VACUUM || c->bcs[1] != BC_VACUUM || c->bcs[2] != BC_VACUUM || TX < 1 || TY < 1) return false;
   const int threads = ((TX * TY + 63) / 64) * 64;
   if (threads > kBlock || 2 * (TX + 2) + 2 * TY > threads) return false;
   const size_t bytes = sizeof(float) * (size_t)c->nc * (TX + 2) * (TY + 2);
@@ -122,10 +122,9 @@ int grid_for(long n) {
 }
 
 void set_geometry(pn_ctx* c, int zchunk) {
-  const int per = c->bc == PN_BC_PERIODIC;
-  c->Ex = c->nx + (per ? 0 : 1);
-  c->Ey = c->ny + (per ? 0 : 1);
-  c->Ez = c->nz + (per ? 0 : 1);
+  c->Ex = c->nx + (c->bcs[0] == BC_PERIODIC ? 0 : 1);
+  c->Ey = c->ny + (c->bcs[1] == BC_PERIODIC ? 0 : 1);
+  c->Ez = c->nz + (c->bcs[2] == BC_PERIODIC ? 0 : 1);
   c->PX = c->Ex + 2;
   c->PY = c->Ey + 2;
   c->plane = c->PX * c->PY;
@@ -155,6 +154,7 @@ StencilArgs base_args(const pn_ctx* c) {
   a.CX = c->CX; a.cplane = c->cplane;
   a.cs = c->cs;
   a.zchunk = c->zchunk; a.nzc = c->nzc; a.ncb = c->ncb; a.nblocks = c->nblocks;
+  a.bcx = c->bcs[0]; a.bcy = c->bcs[1]; a.bcz = c->bcs[2];
   a.invh = 1.0 / c->h;
   a.tsign = 1.0;
   double gp = 1.0;
@@ -234,7 +234,10 @@ struct TuneKey {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, double>> g_tune;
-TuneKey key_of(const pn_ctx* c) { return TuneKey{c->order, c->nx, c->ny, c->nz, c->bc}; }
+// boundary part of the key: bc_x + 3 bc_y + 9 bc_z (0: vacuum everywhere)
+TuneKey key_of(const pn_ctx* c) {
+  return TuneKey{c->order, c->nx, c->ny, c->nz, c->bcs[0] + 3 * c->bcs[1] + 9 * c->bcs[2]};
+}
 }  // namespace
 
 bool tune_lookup(const pn_ctx* c, int* zchunk, double* ms) {
@@ -339,7 +342,7 @@ extern "C" pn_status pn_tune_cache_load(const char* path) {
     double ms = 0.0;
     if (std::sscanf(line, "%d %d %d %d %d %d %lf", &k.order, &k.nx, &k.ny, &k.nz, &k.bc, &z, &ms) != 7 ||
         k.order < 1 || k.order > PN_MAX_ORDER || k.nx < 1 || k.ny < 1 || k.nz < 1 || z < 1 ||
-        (k.bc != PN_BC_VACUUM && k.bc != PN_BC_PERIODIC)) {
+        k.bc < 0 || k.bc >= 27) {
       st = PN_ERR_ARG;
       break;
     }
@@ -357,7 +360,11 @@ pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* 
   if (order < 1 || order > PN_MAX_ORDER) return fail(nullptr, PN_ERR_ARG, "order must be in 1..7");
   if (!grid || !med) return fail(nullptr, PN_ERR_ARG, "grid or medium is NULL");
   if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail(nullptr, PN_ERR_ARG, "grid dimensions must be >= 1");
-  if (grid->bc != PN_BC_VACUUM && grid->bc != PN_BC_PERIODIC) return fail(nullptr, PN_ERR_ARG, "unknown boundary type");
+  int bcs[3];
+  for (int d = 0; d < 3; ++d) bcs[d] = grid->bc == PN_BC_PER_AXIS ? grid->bc_axis[d] : grid->bc;
+  for (int d = 0; d < 3; ++d)
+    if (bcs[d] != PN_BC_VACUUM && bcs[d] != PN_BC_PERIODIC && bcs[d] != PN_BC_NEUMANN)
+      return fail(nullptr, PN_ERR_ARG, "unknown boundary type");
   if (!med->sigma_t || !med->albedo) return fail(nullptr, PN_ERR_ARG, "medium arrays are NULL");
   if (!(med->g > -1.f && med->g < 1.f)) return fail(nullptr, PN_ERR_ARG, "g must be in (-1, 1)");
   if (!(med->sigma_t_min >= 0.f) || !std::isfinite(med->sigma_t_min)) return fail(nullptr, PN_ERR_ARG, "sigma_t_min must be finite and >= 0");
@@ -368,12 +375,12 @@ pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* 
   c->order = order;
   c->nc = (order + 1) * (order + 1);
   c->nx = grid->nx; c->ny = grid->ny; c->nz = grid->nz; c->bc = grid->bc;
+  for (int d = 0; d < 3; ++d) c->bcs[d] = bcs[d];
   c->h = grid->h > 0.0 ? grid->h : 1.0 / grid->nx;
   c->g = med->g;
   c->thr = med->sigma_t_min;
   c->stream = (hipStream_t)stream;
   long n = 0;
-  const int per = c->bc == PN_BC_PERIODIC;
   for (int k = 0; k < c->nc; ++k) {
     int p[3];
     int l = 0;
@@ -386,7 +393,7 @@ pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* 
     long sz = 1;
     for (int d = 0; d < 3; ++d) {
       c->cls[k][d] = p[d];
-      c->ext[k][d] = dims[d] + (per ? 0 : p[d]);
+      c->ext[k][d] = dims[d] + (c->bcs[d] == BC_PERIODIC ? 0 : p[d]);
       sz *= c->ext[k][d];
     }
     c->off[k] = (int)n;
@@ -437,7 +444,8 @@ pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* 
 
   SETUP_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
   hipLaunchKernelGGL(k_medium_prep, dim3(grid_for(pcells)), dim3(kBlock), 0, c->stream, med->sigma_t,
-                     med->albedo, c->thr, c->nx, c->ny, c->nz, per, c->med32, c->med, c->flag);
+                     med->albedo, c->thr, c->nx, c->ny, c->nz, c->bcs[0] == BC_PERIODIC, c->bcs[1] == BC_PERIODIC,
+                     c->bcs[2] == BC_PERIODIC, c->med32, c->med, c->flag);
   SETUP_HIP(hipGetLastError());
   SETUP_HIP(hipMemcpyAsync(c->flag_host, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   SETUP_HIP(hipStreamSynchronize(c->stream));
@@ -522,6 +530,7 @@ extern "C" pn_status pn_layout_query(const pn_ctx* c, pn_layout* L) {
   std::memset(L, 0, sizeof(*L));
   L->order = c->order; L->ncoeff = c->nc;
   L->nx = c->nx; L->ny = c->ny; L->nz = c->nz; L->bc = c->bc;
+  for (int d = 0; d < 3; ++d) L->bc_axis[d] = c->bcs[d];
   L->n_unknowns = c->n;
   for (int k = 0; k < c->nc; ++k) {
     for (int d = 0; d < 3; ++d) { L->cls[k][d] = c->cls[k][d]; L->ext[k][d] = c->ext[k][d]; }
@@ -949,6 +958,10 @@ static const float* r0_as_float(const T* r) {
   else return nullptr;  // learned steps run in the FP32 solve only
 }
 
+static double ms_since(const std::chrono::steady_clock::time_point& t) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+}
+
 // Iterative refinement around CGLS on the padded lattice.  b32 holds Q and
 // x64 the FP64 iterate on entry; x64 holds the result on exit.
 template <typename T>
@@ -1000,7 +1013,10 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     pn_status e = ensure_net_bufs(c);
     if (e != PN_OK) return e;
   }
+  double t_res = 0.0, t_kry = 0.0, t_net = 0.0;
+  int starts = 0;
   if (learned && !o.use_guess) {
+    const auto tl = std::chrono::steady_clock::now();
     double sc = 0.0, ratio = 1.0;
     pn_status e = net_predict(c, c->b32, ss);
     if (e == PN_OK) e = net_scale(c, c->b32, ss, &sc, &ratio);
@@ -1012,13 +1028,16 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
       PN_HIP(hipGetLastError());
       if (info) info->learned_steps += 1;
     }
+    t_net += ms_since(tl);
   }
   bool corrected = false;
   for (;;) {
+    const auto tr = std::chrono::steady_clock::now();
     pn_status e = residual<T>(c, c->b32, c->x64, r0, ss);
     if (e != PN_OK) return e;
     PN_HIP(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, ss));
     PN_HIP(hipStreamSynchronize(ss));
+    t_res += ms_since(tr);
     const DevState h = *c->st_host;
     ++outer;
     bnorm = std::sqrt(h.bb2);
@@ -1037,10 +1056,12 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     if (h.breakdown) { result = PN_ERR_BREAKDOWN; break; }
     // learned correction x += s u, u the prediction for the residual r0
     if (learned && o.learned == PN_LEARNED_GUESS_CORRECT && !corrected) {
+      const auto tl = std::chrono::steady_clock::now();
       double sc = 0.0, ratio = 1.0;
       pn_status e = net_predict(c, r0_as_float(r0), ss);
       if (e == PN_OK) e = net_scale(c, r0_as_float(r0), ss, &sc, &ratio);
       if (e != PN_OK) return e;
+      t_net += ms_since(tl);
       if (ratio < 0.9 && std::isfinite(sc)) {
         hipLaunchKernelGGL(k_axpby64, dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, c->x64, (const double*)c->u64, 1.0,
                            sc, (long)c->nv);
@@ -1051,6 +1072,8 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
       }
     }
     corrected = false;
+    const auto tk = std::chrono::steady_clock::now();
+    ++starts;
     // inner solve  A d = r0  from d = 0
     // relative reduction asked of this inner solve: inner_tol, but no further
     // than the outer tolerance needs (FP64 Krylov: all the way)
@@ -1085,6 +1108,7 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     }
     hipLaunchKernelGGL((k_axpy64<T>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, c->x64, (const T*)d, (long)c->nv);
     PN_HIP(hipGetLastError());
+    t_kry += ms_since(tk);
   }
   if (info) {
     info->status = result;
@@ -1092,6 +1116,12 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     info->inner_iters = c->st_host->iters;
     info->rel_residual = rel;
     info->bnorm = bnorm;
+    info->t_ms[PN_PHASE_RESIDUAL] = t_res;
+    info->t_ms[PN_PHASE_KRYLOV] = t_kry;
+    info->t_ms[PN_PHASE_LEARNED] = t_net;
+    const SolveBytes sb = solve_bytes(c, sizeof(T) == 8, cg, eq);
+    info->bytes = sb.per_iter * info->inner_iters + sb.per_start * starts + sb.per_resid * outer;
+    info->achieved_gbs = (t_res + t_kry) > 0.0 ? info->bytes / ((t_res + t_kry) * 1e6) : 0.0;
   }
   return result;
 }
@@ -1134,13 +1164,20 @@ extern "C" pn_status pn_solve(pn_ctx* c, const float* rhs, double* x, double tol
     hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, c->x64, (long)c->nv, 0.0);
     PN_HIP(hipGetLastError());
   }
+  PN_HIP(hipStreamSynchronize(ss));
+  const double t_setup = ms_since(t0);
   pn_status s = (o.precision == PN_FP64) ? solve_impl<double>(c, tol, o, info) : solve_impl<float>(c, tol, o, info);
+  const auto tf = std::chrono::steady_clock::now();
   // padded -> packed result (also after a failed solve: x is the last iterate)
   PN_HIP((launch_pack<double, double, 1>(c, c->x64, x, ss)));
   PN_HIP(hipEventRecord(c->ev_out, ss));
   PN_HIP(hipStreamWaitEvent(c->stream, c->ev_out, 0));
   PN_HIP(hipStreamSynchronize(ss));
-  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->t_ms[PN_PHASE_SETUP] = t_setup;
+    info->t_ms[PN_PHASE_FINISH] = ms_since(tf);
+  }
   if (s == PN_ERR_NOT_CONVERGED) fail(c, s, "tolerance not reached within max_iter / max_refine");
   if (s == PN_ERR_BREAKDOWN) fail(c, s, "CGLS breakdown");
   if (s == PN_ERR_NONFINITE) fail(c, s, "non-finite residual");

@@ -26,7 +26,7 @@
 namespace {
 
 struct Group {
-  int order = 0, per = 0;
+  int order = 0, gen = 0;  // gen: some axis is not vacuum (general-boundary kernels)
   int2* work = nullptr;         // device list of the systems in the current launch set
   int nwork = 0;
   std::vector<int2> full;       // every (system, tile) of the group
@@ -105,15 +105,15 @@ hipError_t launch_group(const Group& g, int kind, const BatchLaunch& proto, hipS
   BatchLaunch bl = proto;
   bl.work = g.work;
   bl.nwork = g.nwork;
-  const bool per = g.per != 0;
+  const bool gen = g.gen != 0;
   switch (g.order) {
-    case 1: return launch_batch_order<1>(kind, per, bl, s);
-    case 2: return launch_batch_order<2>(kind, per, bl, s);
-    case 3: return launch_batch_order<3>(kind, per, bl, s);
-    case 4: return launch_batch_order<4>(kind, per, bl, s);
-    case 5: return launch_batch_order<5>(kind, per, bl, s);
-    case 6: return launch_batch_order<6>(kind, per, bl, s);
-    case 7: return launch_batch_order<7>(kind, per, bl, s);
+    case 1: return launch_batch_order<1>(kind, gen, bl, s);
+    case 2: return launch_batch_order<2>(kind, gen, bl, s);
+    case 3: return launch_batch_order<3>(kind, gen, bl, s);
+    case 4: return launch_batch_order<4>(kind, gen, bl, s);
+    case 5: return launch_batch_order<5>(kind, gen, bl, s);
+    case 6: return launch_batch_order<6>(kind, gen, bl, s);
+    case 7: return launch_batch_order<7>(kind, gen, bl, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -334,7 +334,7 @@ extern "C" pn_status pn_batch_setup(int nprob, const pn_problem* probs, int nrhs
   std::map<std::pair<int, int>, std::vector<int2>> lists;
   for (int p = 0; p < nprob; ++p) {
     pn_ctx* c = b->prob[p];
-    auto& w = lists[{c->order, c->bc == PN_BC_PERIODIC ? 1 : 0}];
+    auto& w = lists[{c->order, (c->bcs[0] != BC_VACUUM || c->bcs[1] != BC_VACUUM || c->bcs[2] != BC_VACUUM) ? 1 : 0}];
     for (int L = 0; L < c->nblocks; ++L)
       for (int r = 0; r < nrhs; ++r) w.push_back(make_int2(p * nrhs + r, L));
   }
@@ -342,7 +342,7 @@ extern "C" pn_status pn_batch_setup(int nprob, const pn_problem* probs, int nrhs
     if (kv.second.size() >= (size_t)INT32_MAX) { b->err = "work list too long"; return bail(PN_ERR_ARG); }
     Group g;
     g.order = kv.first.first;
-    g.per = kv.first.second;
+    g.gen = kv.first.second;
     g.nwork = (int)kv.second.size();
     SETUP_B(hipMalloc(&g.work, sizeof(int2) * g.nwork));
     SETUP_B(hipMemcpy(g.work, kv.second.data(), sizeof(int2) * g.nwork, hipMemcpyHostToDevice));
@@ -574,6 +574,9 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
       info[i].rel_residual = rel[i];
       info[i].bnorm = bnorm[i];
       info[i].seconds = secs;
+      const SolveBytes sb = solve_bytes(b->prob[i / b->nrhs], false, cg, eq);
+      info[i].bytes = sb.per_iter * info[i].inner_iters + sb.per_start * std::max(outer[i] - 1, 0) +
+                      sb.per_resid * outer[i];
     }
     if (status[i] != PN_OK && first_bad < 0) { first_bad = i; result = (pn_status)status[i]; }
   }

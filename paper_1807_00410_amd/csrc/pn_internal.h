@@ -47,6 +47,7 @@ using namespace pn;
 struct pn_ctx {
   int order = 0, nc = 0;
   int nx = 0, ny = 0, nz = 0, bc = 0;
+  int bcs[3] = {0, 0, 0};  // boundary type per axis (BC_VACUUM / BC_PERIODIC / BC_NEUMANN)
   double h = 0.0;
   float g = 0.f, thr = 0.f;
   hipStream_t stream = nullptr;   // caller's stream
@@ -113,6 +114,28 @@ pn_status fail(pn_ctx* c, pn_status s, const std::string& msg);
 int grid_for(long n);
 void set_geometry(pn_ctx* c, int zchunk);
 StencilArgs base_args(const pn_ctx* c);
+// Algorithmic bytes of the solve's kernels (vector elements read and written
+// per unknown, the medium at 8 bytes per cell per stencil pass).
+struct SolveBytes {
+  double per_iter, per_start, per_resid;
+};
+inline SolveBytes solve_bytes(const pn_ctx* c, bool fp64, bool cg, bool eq) {
+  const double n = (double)c->n, cells = (double)c->nx * c->ny * c->nz;
+  SolveBytes b;
+  if (fp64) {  // CGLS in FP64: A p (16), A^T r' with r' = r - alpha q (32), x/p update (40)
+    b.per_iter = 88.0 * n + 16.0 * cells;
+    b.per_start = 16.0 * n + 8.0 * cells + 32.0 * n;  // s = A^T r0, p = s, d = 0, x += d
+  } else if (cg) {  // (W) A p (8), s -= alpha A^T q (12), x/p update (20)
+    b.per_iter = 40.0 * n + 16.0 * cells;
+    b.per_start = 8.0 * n + 8.0 * cells + 8.0 * n + 4.0 * n + 12.0 * n + (eq ? 8.0 * n + 8.0 * cells : 0.0);
+  } else {  // CGLS: A p (8), r' = r - alpha q and A^T r' (16), x/p update (20)
+    b.per_iter = 44.0 * n + 16.0 * cells;
+    b.per_start = 8.0 * n + 8.0 * cells + 8.0 * n + 4.0 * n + 12.0 * n;
+  }
+  b.per_resid = 16.0 * n + 8.0 * cells;  // x FP64, Q, r
+  return b;
+}
+
 // Context with geometry and medium; the Krylov workspace only if `workspace`.
 pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* stream, bool workspace,
                     pn_ctx** out);
@@ -155,7 +178,7 @@ inline hipError_t launch_pack(const pn_ctx* c, const TS* src, TD* dst, hipStream
 // other modes always do.
 template <typename T, int MODE, typename TO>
 inline hipError_t launch_stencil(const pn_ctx* c, const StencilArgs& a, hipStream_t s) {
-  const bool per = c->bc == PN_BC_PERIODIC;
+  const bool gen = c->bcs[0] != BC_VACUUM || c->bcs[1] != BC_VACUUM || c->bcs[2] != BC_VACUUM;
   const bool norm = !(MODE == M_APPLY && a.partials == nullptr);
   int kind;
   if constexpr (sizeof(T) == 4)
@@ -167,13 +190,13 @@ inline hipError_t launch_stencil(const pn_ctx* c, const StencilArgs& a, hipStrea
   else if constexpr (MODE == M_TRANSR) kind = K_F64_TRANSR;
   else kind = (sizeof(TO) == 4) ? K_F64_RESID32 : K_F64_RESID64;
   switch (c->order) {
-    case 1: return launch_order<1>(kind, per, norm, a, s);
-    case 2: return launch_order<2>(kind, per, norm, a, s);
-    case 3: return launch_order<3>(kind, per, norm, a, s);
-    case 4: return launch_order<4>(kind, per, norm, a, s);
-    case 5: return launch_order<5>(kind, per, norm, a, s);
-    case 6: return launch_order<6>(kind, per, norm, a, s);
-    case 7: return launch_order<7>(kind, per, norm, a, s);
+    case 1: return launch_order<1>(kind, gen, norm, a, s);
+    case 2: return launch_order<2>(kind, gen, norm, a, s);
+    case 3: return launch_order<3>(kind, gen, norm, a, s);
+    case 4: return launch_order<4>(kind, gen, norm, a, s);
+    case 5: return launch_order<5>(kind, gen, norm, a, s);
+    case 6: return launch_order<6>(kind, gen, norm, a, s);
+    case 7: return launch_order<7>(kind, gen, norm, a, s);
     default: return hipErrorInvalidValue;
   }
 }

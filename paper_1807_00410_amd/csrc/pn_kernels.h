@@ -65,13 +65,24 @@ enum Mode { M_APPLY = 0, M_TRANSR = 1, M_RESID = 2, M_SUPD = 3, M_APPLY_EQ = 4, 
 // Internal vectors live on a padded lattice shared by every coefficient:
 // coefficient k occupies [k*cs, (k+1)*cs); lattice point (x, y, z) of any
 // class sits at ((z+1)*PY + (y+1))*PX + (x+1) with PX = Ex + 2, PY = Ey + 2,
-// where Ex = nx + 1 (vacuum) or nx (periodic).  Entries outside a
-// coefficient's class extent -- the one-point halo and, for a class centred
-// along d, the position x_d = n_d -- are zero and stay zero: kernels never
-// store there and every element-wise update maps 0 to 0.  That makes every
-// neighbour load unconditional (vacuum: an out-of-domain read hits a zero).
-// Cells are padded the same way, their halo holding clamped (vacuum) or
-// wrapped (periodic) copies, so the parameter reads need no clamping either.
+// where Ex = nx + 1 (vacuum / Neumann along x) or nx (periodic along x).
+// Entries outside a coefficient's class extent -- the one-point halo and, for
+// a class centred along d, the position x_d = n_d -- are zero and stay zero:
+// kernels never store there and every element-wise update maps 0 to 0.
+// That makes every neighbour load unconditional (vacuum: an out-of-domain read
+// hits a zero).  Cells are padded the same way, their halo holding clamped
+// (vacuum, Neumann) or wrapped (periodic) copies, so the parameter reads need
+// no clamping either.
+//
+// Boundary types per axis (BC_*): vacuum = the paper's Dirichlet mode (an
+// entry referencing a location outside the domain is dropped: the zero halo);
+// periodic = wrap-around; Neumann = the entry moves to the coefficient at the
+// closest location inside the domain (section "Runtime").  Only the
+// differences of face-centred rows on a boundary face reach outside, and there
+// the two samples of the centred input land on the same coefficient, so under
+// Neumann those differences vanish from A; in A^T the face values on the two
+// boundary faces drop out of the differences of the centred rows next to them.
+enum { BC_VACUUM = 0, BC_PERIODIC = 1, BC_NEUMANN = 2 };
 struct StencilArgs {
   int nx, ny, nz;
   int Ex, Ey, Ez;      // lattice points per axis
@@ -79,6 +90,7 @@ struct StencilArgs {
   int CX, cplane;      // padded cell pitches: CX = nx + 2, cplane = CX*(ny + 2)
   long long cs;        // coefficient stride (elements)
   int zchunk, nzc, ncb, nblocks;
+  int bcx, bcy, bcz;   // boundary type per axis (the general-boundary kernels)
   double invh;         // 1 / h
   double tsign;        // +1: A, -1: A^T
   double omg[8];       // 1 - g^l, l = 0..7
@@ -155,7 +167,8 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 
 // --------------------------------------------------------------- stencil --
 // T: arithmetic / vector type of the input (float or double).  TO: output
-// element type.  PER: periodic boundary.  NORM: write the FP64 block partial
+// element type.  GEN: general boundary types per axis (a.bcx, a.bcy, a.bcz);
+// otherwise vacuum on every axis.  NORM: write the FP64 block partial
 // sums of the squares below to a.partials (per thread, squares are summed in
 // T over the rows of one class -- at most 10 terms -- then added in FP64).
 //   M_APPLY  y = op(x)                         [||y||^2]
@@ -167,7 +180,7 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 // W is diagonal: w = 1 / (d^2 + sum of the squared transport entries of the
 // row), d the row's diagonal -- the inverse squared 2-norm of the row of A
 // away from the boundary.
-template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
+template <int N, typename T, int MODE, typename TO, bool GEN, bool NORM>
 __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) {
   using TB = Table<N>;
   constexpr int NC = TB::NC;
@@ -193,17 +206,21 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
   // Lane offsets inside a padded plane (own point and the four in-plane
   // neighbours), kept as 32-bit BYTE offsets: every access is then a uniform
   // 64-bit base (coefficient, plane) in SGPRs plus one 32-bit VGPR offset.
+  const bool perx = GEN && a.bcx == BC_PERIODIC, pery = GEN && a.bcy == BC_PERIODIC;
+  const bool perz = GEN && a.bcz == BC_PERIODIC;
   unsigned o, oxp, oxm, oyp, oym;
   {
     const int oi = (y + 1) * a.PX + (x + 1);
-    int ixp, ixm, iyp, iym;
-    if constexpr (PER) {
-      ixp = (y + 1) * a.PX + (x + 1 == a.nx ? 0 : x + 1) + 1;
-      ixm = (y + 1) * a.PX + (x == 0 ? a.nx - 1 : x - 1) + 1;
-      iyp = ((y + 1 == a.ny ? 0 : y + 1) + 1) * a.PX + x + 1;
-      iym = ((y == 0 ? a.ny - 1 : y - 1) + 1) * a.PX + x + 1;
-    } else {
-      ixp = oi + 1; ixm = oi - 1; iyp = oi + a.PX; iym = oi - a.PX;
+    int ixp = oi + 1, ixm = oi - 1, iyp = oi + a.PX, iym = oi - a.PX;
+    if constexpr (GEN) {
+      if (perx) {
+        ixp = (y + 1) * a.PX + (x + 1 == a.nx ? 0 : x + 1) + 1;
+        ixm = (y + 1) * a.PX + (x == 0 ? a.nx - 1 : x - 1) + 1;
+      }
+      if (pery) {
+        iyp = ((y + 1 == a.ny ? 0 : y + 1) + 1) * a.PX + x + 1;
+        iym = ((y == 0 ? a.ny - 1 : y - 1) + 1) * a.PX + x + 1;
+      }
     }
     o = (unsigned)oi * (unsigned)sizeof(T);
     oxp = (unsigned)ixp * (unsigned)sizeof(T);
@@ -216,15 +233,31 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
   // padded cell (x-1, y-1) of a cell plane, bytes
   const unsigned mo = (unsigned)(y * a.CX + x) * (unsigned)sizeof(float2);
   const unsigned mcx = (unsigned)a.CX * (unsigned)sizeof(float2);
-  const bool okx0 = PER || x < a.nx;  // store predicate of classes centred in x
-  const bool oky0 = PER || y < a.ny;
+  const bool okx0 = perx || x < a.nx;  // store predicate of classes centred in x
+  const bool oky0 = pery || y < a.ny;
+  // Neumann weights of the differences along x and y (1 elsewhere): A drops
+  // the backward difference of face rows on a boundary face (nb); A^T drops
+  // the boundary-face samples from the forward difference of centred rows
+  // (nl: the face below the row, nh: the face above it)
+  T nbx = T(1), nlx = T(1), nhx = T(1), nby = T(1), nly = T(1), nhy = T(1);
+  if constexpr (GEN) {
+    const bool fwd = a.tsign > 0.0;
+    if (a.bcx == BC_NEUMANN) {
+      if (fwd) nbx = (x == 0 || x == a.nx) ? T(0) : T(1);
+      else { nlx = x == 0 ? T(0) : T(1); nhx = x + 1 == a.nx ? T(0) : T(1); }
+    }
+    if (a.bcy == BC_NEUMANN) {
+      if (fwd) nby = (y == 0 || y == a.ny) ? T(0) : T(1);
+      else { nly = y == 0 ? T(0) : T(1); nhy = y + 1 == a.ny ? T(0) : T(1); }
+    }
+  }
 
   // padded plane offset (elements) of lattice plane z (periodic planes wrap)
   // The offset goes through readfirstlane: it is uniform anyway, and the
   // opaque value keeps loop strength reduction from turning every one of the
   // ~100 address streams into its own 64-bit induction variable in VGPRs.
   auto zoff = [&](int z) -> long long {
-    if constexpr (PER) z = wrapi(z, a.nz);
+    if (perz) z = wrapi(z, a.nz);
     return (long long)__builtin_amdgcn_readfirstlane((z + 1) * a.plane);
   };
   // Element offset of (coefficient, plane) as an opaque uniform 32-bit value:
@@ -266,7 +299,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
       });
     }
     T msa[8], mss[8];  // cells of the plane below (0..3) and of this plane (4..7)
-    cells(PER ? wrapi(z0 - 1, a.nz) : z0 - 1, msa, mss);
+    cells(perz ? wrapi(z0 - 1, a.nz) : z0 - 1, msa, mss);
 
 #pragma clang loop unroll(disable)
     for (int z = z0; z < z1; ++z) {
@@ -304,7 +337,14 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
 
       // Rows one staggering class at a time: form each (input, axis)
       // difference once, fan it out to the rows of the class, store them.
-      const bool okz0 = PER || z < a.nz;
+      const bool okz0 = perz || z < a.nz;
+      T nbz = T(1), nlz = T(1), nhz = T(1);  // Neumann weights along z (as for x, y)
+      if constexpr (GEN) {
+        if (a.bcz == BC_NEUMANN) {
+          if (a.tsign > 0.0) nbz = (z == 0 || z == a.nz) ? T(0) : T(1);
+          else { nlz = z == 0 ? T(0) : T(1); nhz = z + 1 == a.nz ? T(0) : T(1); }
+        }
+      }
       sfor<8>([&](auto Cc) {
         constexpr int c = decltype(Cc)::value;
         if constexpr (TB::class_has_rows(c)) {
@@ -337,11 +377,17 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
             if constexpr (first) {
               constexpr int p = cls_axis(cp.kp, cp.d);
               if constexpr (cp.d == 2) {
-                dcur = p ? nb[cp.kp] - cur[cp.kp] : cur[cp.kp] - nb[cp.kp];
+                if constexpr (GEN) dcur = p ? nhz * nb[cp.kp] - nlz * cur[cp.kp] : nbz * (cur[cp.kp] - nb[cp.kp]);
+                else dcur = p ? nb[cp.kp] - cur[cp.kp] : cur[cp.kp] - nb[cp.kp];
               } else {
                 const unsigned lo = (cp.d == 0) ? (p ? oxp : oxm) : (p ? oyp : oym);
                 const T v = load(std::integral_constant<int, cp.kp>{}, zo, lo);
-                dcur = p ? v - cur[cp.kp] : cur[cp.kp] - v;
+                if constexpr (GEN) {
+                  const T nh = cp.d == 0 ? nhx : nhy, nl = cp.d == 0 ? nlx : nly, nbb = cp.d == 0 ? nbx : nby;
+                  dcur = p ? nh * v - nl * cur[cp.kp] : nbb * (cur[cp.kp] - v);
+                } else {
+                  dcur = p ? v - cur[cp.kp] : cur[cp.kp] - v;
+                }
               }
             }
             acc[cp.k] = fmadd<T>(T(cp.c), dcur, acc[cp.k]);
@@ -398,11 +444,11 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
   }
 }
 
-template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
+template <int N, typename T, int MODE, typename TO, bool GEN, bool NORM>
 __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil(const StencilArgs a) {
   // In the Krylov loop the A p launch also ends once the stop flag is up.
   if (a.st != nullptr && (a.st->done || ((MODE == M_APPLY || MODE == M_APPLY_EQ) && a.st->stop))) return;
-  stencil_body<N, T, MODE, TO, PER, NORM>(a, xcd_remap(blockIdx.x, a.nblocks));
+  stencil_body<N, T, MODE, TO, GEN, NORM>(a, xcd_remap(blockIdx.x, a.nblocks));
 }
 
 // ---------------------------------------------------------------- batch --
@@ -430,7 +476,7 @@ struct BatchLaunch {
   int gate;             // 1: skip systems whose inner solve stopped (Krylov loop)
 };
 
-template <int N, typename T, int MODE, typename TO, bool PER, bool NORM>
+template <int N, typename T, int MODE, typename TO, bool GEN, bool NORM>
 __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil_batch(const BatchLaunch bl) {
   const int2 w = bl.work[xcd_remap(blockIdx.x, bl.nwork)];
   const SysArgs* __restrict__ s = bl.sys + w.x;
@@ -442,7 +488,7 @@ __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil_batch(const 
   a.y = s->vec[bl.iy];
   a.y2 = bl.iy2 >= 0 ? s->vec[bl.iy2] : nullptr;
   a.tsign = bl.tsign;
-  stencil_body<N, T, MODE, TO, PER, NORM>(a, w.y);
+  stencil_body<N, T, MODE, TO, GEN, NORM>(a, w.y);
 }
 
 // ------------------------------------------------------------- finalize --
@@ -657,10 +703,11 @@ __global__ void __launch_bounds__(kBlock) k_axpy64(double* __restrict__ x, const
 
 // Padded cell arrays: med32 = (sigma_a, sigma_s) in FP32 and med = (sigma_t,
 // albedo) with sigma_t raised to the threshold; the one-cell halo holds
-// clamped (vacuum) or wrapped (periodic) copies.  Flags NaN / Inf.
+// clamped (vacuum, Neumann) or wrapped (periodic) copies, per axis.  Flags
+// NaN / Inf.
 static __global__ void __launch_bounds__(kBlock) k_medium_prep(const float* __restrict__ sigma_t,
                                                         const float* __restrict__ albedo, float thr,
-                                                        int nx, int ny, int nz, int periodic,
+                                                        int nx, int ny, int nz, int perx, int pery, int perz,
                                                         float2* __restrict__ med32, float2* __restrict__ med,
                                                         int* bad) {
   const long long CX = nx + 2, CY = ny + 2, n = CX * CY * (nz + 2);
@@ -668,11 +715,9 @@ static __global__ void __launch_bounds__(kBlock) k_medium_prep(const float* __re
   int b = 0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     int px = (int)(i % CX) - 1, py = (int)((i / CX) % CY) - 1, pz = (int)(i / (CX * CY)) - 1;
-    if (periodic) {
-      px = wrapi(px, nx); py = wrapi(py, ny); pz = wrapi(pz, nz);
-    } else {
-      px = min(max(px, 0), nx - 1); py = min(max(py, 0), ny - 1); pz = min(max(pz, 0), nz - 1);
-    }
+    px = perx ? wrapi(px, nx) : min(max(px, 0), nx - 1);
+    py = pery ? wrapi(py, ny) : min(max(py, 0), ny - 1);
+    pz = perz ? wrapi(pz, nz) : min(max(pz, 0), nz - 1);
     const long long src = ((long long)pz * ny + py) * nx + px;
     const float s = sigma_t[src], al = albedo[src];
     if (!isfinite(s) || !isfinite(al)) b = 1;

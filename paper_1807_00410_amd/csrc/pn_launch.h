@@ -21,30 +21,30 @@ enum Kind {
 };
 
 template <int N, typename T, int MODE, typename TO>
-hipError_t launch_flavour(bool per, bool norm, const StencilArgs& a, hipStream_t s) {
+hipError_t launch_flavour(bool gen, bool norm, const StencilArgs& a, hipStream_t s) {
   dim3 grid(a.nblocks), block(kBlock);
   if (MODE == M_APPLY && !norm) {
-    if (per) hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, true, false>), grid, block, 0, s, a);
+    if (gen) hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, true, false>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, false, false>), grid, block, 0, s, a);
   } else {
-    if (per) hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, true, true>), grid, block, 0, s, a);
+    if (gen) hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, true, true>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_stencil<N, T, MODE, TO, false, true>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }
 
 template <int N>
-hipError_t launch_order(int kind, bool per, bool norm, const StencilArgs& a, hipStream_t s) {
+hipError_t launch_order(int kind, bool gen, bool norm, const StencilArgs& a, hipStream_t s) {
   switch (kind) {
-    case K_F32_APPLY: return launch_flavour<N, float, M_APPLY, float>(per, norm, a, s);
-    case K_F32_TRANSR: return launch_flavour<N, float, M_TRANSR, float>(per, true, a, s);
-    case K_F64_APPLY: return launch_flavour<N, double, M_APPLY, double>(per, norm, a, s);
-    case K_F64_TRANSR: return launch_flavour<N, double, M_TRANSR, double>(per, true, a, s);
-    case K_F64_RESID32: return launch_flavour<N, double, M_RESID, float>(per, true, a, s);
-    case K_F64_RESID64: return launch_flavour<N, double, M_RESID, double>(per, true, a, s);
-    case K_F32_SUPD: return launch_flavour<N, float, M_SUPD, float>(per, true, a, s);
-    case K_F32_APPLY_EQ: return launch_flavour<N, float, M_APPLY_EQ, float>(per, true, a, s);
-    case K_F32_EQS: return launch_flavour<N, float, M_EQS, float>(per, true, a, s);
+    case K_F32_APPLY: return launch_flavour<N, float, M_APPLY, float>(gen, norm, a, s);
+    case K_F32_TRANSR: return launch_flavour<N, float, M_TRANSR, float>(gen, true, a, s);
+    case K_F64_APPLY: return launch_flavour<N, double, M_APPLY, double>(gen, norm, a, s);
+    case K_F64_TRANSR: return launch_flavour<N, double, M_TRANSR, double>(gen, true, a, s);
+    case K_F64_RESID32: return launch_flavour<N, double, M_RESID, float>(gen, true, a, s);
+    case K_F64_RESID64: return launch_flavour<N, double, M_RESID, double>(gen, true, a, s);
+    case K_F32_SUPD: return launch_flavour<N, float, M_SUPD, float>(gen, true, a, s);
+    case K_F32_APPLY_EQ: return launch_flavour<N, float, M_APPLY_EQ, float>(gen, true, a, s);
+    case K_F32_EQS: return launch_flavour<N, float, M_EQS, float>(gen, true, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -52,22 +52,22 @@ hipError_t launch_order(int kind, bool per, bool norm, const StencilArgs& a, hip
 // Batched launch over the systems of one order (BatchLaunch.work); the
 // Krylov kinds always reduce.
 template <int N, typename T, int MODE, typename TO>
-hipError_t launch_batch_flavour(bool per, const BatchLaunch& bl, hipStream_t s) {
+hipError_t launch_batch_flavour(bool gen, const BatchLaunch& bl, hipStream_t s) {
   dim3 grid(bl.nwork), block(kBlock);
-  if (per) hipLaunchKernelGGL((k_stencil_batch<N, T, MODE, TO, true, true>), grid, block, 0, s, bl);
+  if (gen) hipLaunchKernelGGL((k_stencil_batch<N, T, MODE, TO, true, true>), grid, block, 0, s, bl);
   else hipLaunchKernelGGL((k_stencil_batch<N, T, MODE, TO, false, true>), grid, block, 0, s, bl);
   return hipGetLastError();
 }
 
 template <int N>
-hipError_t launch_batch_order(int kind, bool per, const BatchLaunch& bl, hipStream_t s) {
+hipError_t launch_batch_order(int kind, bool gen, const BatchLaunch& bl, hipStream_t s) {
   switch (kind) {
-    case K_F32_APPLY: return launch_batch_flavour<N, float, M_APPLY, float>(per, bl, s);
-    case K_F32_TRANSR: return launch_batch_flavour<N, float, M_TRANSR, float>(per, bl, s);
-    case K_F32_SUPD: return launch_batch_flavour<N, float, M_SUPD, float>(per, bl, s);
-    case K_F32_APPLY_EQ: return launch_batch_flavour<N, float, M_APPLY_EQ, float>(per, bl, s);
-    case K_F32_EQS: return launch_batch_flavour<N, float, M_EQS, float>(per, bl, s);
-    case K_F64_RESID32: return launch_batch_flavour<N, double, M_RESID, float>(per, bl, s);
+    case K_F32_APPLY: return launch_batch_flavour<N, float, M_APPLY, float>(gen, bl, s);
+    case K_F32_TRANSR: return launch_batch_flavour<N, float, M_TRANSR, float>(gen, bl, s);
+    case K_F32_SUPD: return launch_batch_flavour<N, float, M_SUPD, float>(gen, bl, s);
+    case K_F32_APPLY_EQ: return launch_batch_flavour<N, float, M_APPLY_EQ, float>(gen, bl, s);
+    case K_F32_EQS: return launch_batch_flavour<N, float, M_EQS, float>(gen, bl, s);
+    case K_F64_RESID32: return launch_batch_flavour<N, double, M_RESID, float>(gen, bl, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -25,6 +25,19 @@ def _ptr(t, dtype):
     return C.c_void_p(t.data_ptr())
 
 
+def make_grid(dims, h, bc):
+    """pn_grid for a boundary type (int: the same on every axis) or a 3-tuple
+    of types per axis (x, y, z)."""
+    if isinstance(bc, (tuple, list)):
+        if len(bc) != 3:
+            raise ValueError("bc must be one type or three")
+        axes = tuple(int(v) for v in bc)
+        code = axes[0] if axes[0] == axes[1] == axes[2] else L.PN_BC_PER_AXIS
+    else:
+        code, axes = int(bc), (0, 0, 0)
+    return L.PnGrid(int(dims[0]), int(dims[1]), int(dims[2]), float(h), code, (C.c_int * 3)(*axes))
+
+
 class Layout:
     """Staggered SoA layout reported by pn_layout_query."""
 
@@ -33,6 +46,7 @@ class Layout:
         self.ncoeff = raw.ncoeff
         self.dims = (raw.nx, raw.ny, raw.nz)
         self.bc = raw.bc
+        self.bc_axis = tuple(raw.bc_axis)
         self.n = int(raw.n_unknowns)
         self.cls = [tuple(raw.cls[k]) for k in range(self.ncoeff)]
         self.ext = [tuple(raw.ext[k]) for k in range(self.ncoeff)]
@@ -51,7 +65,7 @@ class Solver:
         self.lib = L.load()
         st = sigma_t.contiguous()
         al = albedo.contiguous()
-        grid = L.PnGrid(int(dims[0]), int(dims[1]), int(dims[2]), float(h), int(bc))
+        grid = make_grid(dims, h, bc)
         med = L.PnMedium(_ptr(st, torch.float32), _ptr(al, torch.float32), float(g), float(sigma_t_min))
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
@@ -213,7 +227,9 @@ def _info(rc, info):
     return dict(status=rc, outer_iters=info.outer_iters, inner_iters=info.inner_iters,
                 rel_residual=info.rel_residual, bnorm=info.bnorm, seconds=info.seconds,
                 history=[info.history[i] for i in range(info.nhistory)],
-                learned_steps=info.learned_steps, learned_ratio=info.learned_ratio)
+                learned_steps=info.learned_steps, learned_ratio=info.learned_ratio,
+                t_ms={name: info.t_ms[i] for i, name in enumerate(L.PHASES)}, bytes=info.bytes,
+                achieved_gbs=info.achieved_gbs)
 
 
 class Batch:
@@ -232,7 +248,7 @@ class Batch:
             al = al.contiguous()
             keep += [st, al]
             arr[i].order = int(order)
-            arr[i].grid = L.PnGrid(int(dims[0]), int(dims[1]), int(dims[2]), float(h), int(bc))
+            arr[i].grid = make_grid(dims, h, bc)
             arr[i].medium = L.PnMedium(_ptr(st, torch.float32), _ptr(al, torch.float32), float(g), float(stmin))
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
