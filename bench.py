@@ -3,7 +3,8 @@
 
 One step = one complete solve A u = Q from u = 0 to ||Q - A u|| <= 1e-8 ||Q||
 (FP32 stencil + Krylov vectors, FP64 dot products, scalars and refinement
-residual), inputs resident in HBM.  Prints one JSON line.
+residual; the inner solver is the even-parity PCG on the Schur complement of
+the even bands), inputs resident in HBM.  Prints one JSON line.
 
 Also reported (JSON keys):
   roofline      the kernel of the Krylov loop that takes the most time per
@@ -13,7 +14,11 @@ Also reported (JSON keys):
                 launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
                 summary when it was taken on the current kernel sources.
   loop_kernels  the same figures for every kernel of the loop (the plain
-                apply, q = W A p, s -= alpha A^T q, the x/p update).
+                apply; w_o = -D_o^-1 T_oe p_e, q_e = S p_e and the two PCG
+                vector passes; and the kernels of the normal-equation loop,
+                q = W A p, s -= alpha A^T q, the x/p update).
+  cg_eq_normal_equations  the previous default inner solver (CG on the
+                row-equilibrated normal equations) on the same system.
   cpu_baseline  the C/OpenMP FP64 oracle's CGLS (oracle/pn_ref.c) timed for a
                 bounded number of iterations on the full P5 128^3 system on
                 this host's cores, scaled by the iterations the oracle's CGLS
@@ -63,14 +68,22 @@ def load_traffic(kernel_hash, kernel):
     return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
-# algorithmic HBM bytes of the Krylov-loop kernels: per unknown (FP32 vector
-# elements read + written) and whether the medium (8 B per cell) is read
+# algorithmic HBM bytes of the Krylov-loop kernels as a function of the
+# unknowns n, the even-band unknowns ne and the cells: FP32 vector elements
+# read + written, and the medium (8 B per cell) for the stencil passes
 LOOP_KERNELS = (
-    ("apply", 8, True, "k_stencil<5,float,APPLY>: y = A x"),
-    ("apply_eq", 8, True, "k_stencil<5,float,APPLY_EQ>: q = W A p, <A p, W A p> partials"),
-    ("supd", 12, True, "k_stencil<5,float,SUPD>: s -= alpha A^T q, ||s||^2 partials"),
-    ("update", 20, False, "k_update_xp<float>: x += alpha p, p = s + beta p"),
+    ("apply", lambda n, ne, c: 8 * n + 8 * c, "k_stencil<5,float,APPLY>: y = A x"),
+    ("odd_w", lambda n, ne, c: 4 * ne + 4 * (n - ne) + 8 * c,
+     "k_stencil<5,float,ODD_W>: w_o = -D_o^-1 T_oe p_e (odd rows)"),
+    ("even_s", lambda n, ne, c: 4 * n + 4 * ne + 8 * c,
+     "k_stencil<5,float,EVEN_S>: q_e = D_e p_e + T_eo w_o, <p, q> partials"),
+    ("pcg_xr", lambda n, ne, c: 28 * ne, "k_pcg_vec<1>: x += alpha p, r -= alpha q, <r, M r>, <r, r> partials"),
+    ("pcg_p", lambda n, ne, c: 16 * ne, "k_pcg_vec<2>: p = M r + beta p"),
+    ("apply_eq", lambda n, ne, c: 8 * n + 8 * c, "k_stencil<5,float,APPLY_EQ>: q = W A p (normal-equation loop)"),
+    ("supd", lambda n, ne, c: 12 * n + 8 * c, "k_stencil<5,float,SUPD>: s -= alpha A^T q (normal-equation loop)"),
+    ("update", lambda n, ne, c: 20 * n, "k_update_xp<float>: x += alpha p, p = s + beta p (normal-equation loop)"),
 )
+SCHUR_LOOP = ("odd_w", "even_s", "pcg_xr", "pcg_p")
 
 
 def oracle_run(tag):
@@ -280,9 +293,10 @@ def bench_batch(args, quiet=False):
 
 
 def profile_kernels(args):
-    """Profiling mode for rocprofv3 (--profile-kernels): runs each kernel of
-    the FP32 Krylov loop of the P5 nebula workload (plain apply, q = W A p,
-    s -= alpha A^T q, x/p update) `--profile-iters` times in its in-loop form
+    """Profiling mode for rocprofv3 (--profile-kernels): runs each listed
+    kernel of the FP32 Krylov loops of the P5 nebula workload (the plain
+    apply; the even-parity loop odd_w, even_s, pcg_xr, pcg_p; the
+    normal-equation loop apply_eq, supd, update) `--profile-iters` times in its in-loop form
     at a fixed z-chunk, then three plain 1 GiB device copies whose counter
     readings calibrate FETCH_SIZE / WRITE_SIZE (bytes per copy known).  Prints
     the live timings; the counters come from the profiler."""
@@ -294,10 +308,12 @@ def profile_kernels(args):
                g=m.g, sigma_t_min=m.sigma_t_min)
     s.set_zchunk(args.profile_zchunk)
     cells = m.dims[0] * m.dims[1] * m.dims[2]
-    per_unknown = {"apply": 8, "apply_t": 8, "apply_eq": 8, "supd": 12, "update": 20}
+    ne = s.even_unknowns()
+    nbytes = {name: f for name, f, _ in LOOP_KERNELS}
+    nbytes["apply_t"] = nbytes["apply"]
     for k in args.profile_kernels.split(","):
         ms = s.bench_kernel(k, args.profile_iters)
-        alg = per_unknown[k] * s.n + (8 * cells if k != "update" else 0)
+        alg = nbytes[k](s.n, ne, cells)
         print("%s %.4f ms, %.1f GB/s algorithmic (%d unknowns)" % (k, ms, alg / ms / 1e6, s.n), flush=True)
     a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
@@ -328,7 +344,8 @@ def main():
     ap.add_argument("--workload", choices=("p5", "batch"), default="p5")
     ap.add_argument("--batch-media", type=int, default=48)
     ap.add_argument("--profile-kernels", default=None, metavar="LIST",
-                    help="profiling mode: comma-separated loop kernels (apply, apply_t, apply_eq, supd, update) "
+                    help="profiling mode: comma-separated loop kernels (apply, apply_t, odd_w, even_s, pcg_xr, pcg_p, "
+                         "apply_eq, supd, update) "
                          "run in their in-loop form for rocprofv3, then the counter-calibration copies")
     ap.add_argument("--profile-iters", type=int, default=10)
     ap.add_argument("--profile-zchunk", type=int, default=2)
@@ -393,16 +410,25 @@ def main():
     cells = m.dims[0] * m.dims[1] * m.dims[2]
     khash = source_hash()
     loop = {}
-    for name, per_unknown, medium, desc in LOOP_KERNELS:
+    ne = s.even_unknowns()
+    for name, nbytes, desc in LOOP_KERNELS:
         ms = s.bench_kernel(name, args.apply_iters)
-        alg = per_unknown * s.n + (8 * cells if medium else 0)
+        alg = nbytes(s.n, ne, cells)
         ach = alg / (ms * 1e-3) / 1e9
         loop[name] = {"kernel": desc, "ms": ms, "algorithmic_bytes_per_launch": alg, "achieved": ach,
                       "frac": ach / HBM_PEAK_GBS, "traffic": load_traffic(khash, name)}
         print("[bench] %-8s %.4f ms  %.0f GB/s algorithmic" % (name, ms, ach), file=sys.stderr, flush=True)
-    # the dominant kernel: the most time per iteration of the default solve
-    dom = max(("apply_eq", "supd", "update"), key=lambda k: loop[k]["ms"])
+    # the dominant kernel: the most time per iteration of the default (even-parity) solve
+    dom = max(SCHUR_LOOP, key=lambda k: loop[k]["ms"])
 
+    # the previous default inner solver (CG on the row-equilibrated normal
+    # equations) on the same system
+    ti, ii = timed_solve(s, rhs, torch.zeros_like(x), warmup=0, tol=args.tol, inner_tol=args.inner_tol,
+                         variant="cg_eq")
+    cg_eq = {"seconds": ti, "iters": ii["inner_iters"], "rel_residual": ii["rel_residual"],
+             "speedup_of_default": ti / sec}
+    print("[bench] CG on the equilibrated normal equations: %.3fs iters %d" % (ti, ii["inner_iters"]),
+          file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:
         xx = torch.zeros_like(x)
@@ -470,7 +496,8 @@ def main():
         "config": {"workload": "P%d nebula %d^3 (32 Gaussian blobs x fBm, sigma_t in [0,200], albedo 0.95, "
                                "g=%g, 2 point sources), vacuum boundary, tol %g"
                                % (m.order, args.n, m.g, args.tol),
-                   "unknowns": s.n, "solver": "FP32 CG on the row-equilibrated normal equations + FP64 dots/refinement (plain)",
+                   "unknowns": s.n, "solver": "FP32 even-parity PCG (Jacobi-preconditioned CG on the Schur complement "
+                                             "of the even bands) + FP64 dots/refinement (plain)",
                    "inner_tol": args.inner_tol, "zchunk": zchunk},
         "iters": infos[-1]["inner_iters"],
         "outer_iters": infos[-1]["outer_iters"],
@@ -478,6 +505,9 @@ def main():
         "wall_s_timed_region": total,
         "apply_ms": ms_apply,
         "apply_t_ms": ms_apply_t,
+        "phases_ms": infos[-1]["t_ms"], "solve_algorithmic_bytes": infos[-1]["bytes"],
+        "solve_achieved_GBs": infos[-1]["achieved_gbs"],
+        "cg_eq_normal_equations": cg_eq,
         "fp64_krylov": fp64,
         "fp32_krylov_no_refinement": fp32_single,
         "learned_mixed": learned,

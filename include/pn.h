@@ -124,7 +124,21 @@ typedef struct {
 #define PN_LEARNED_GUESS 1
 #define PN_LEARNED_GUESS_CORRECT 2
 
-/* Krylov variant of the FP32 inner solve.  CGLS: the residual-based CGLS
+/* Krylov variant of the FP32 inner solve.  SCHUR: the even-parity form.  The
+ * transport couples only bands l and l +- 1, and the band parity of a
+ * coefficient is the parity of its staggering class, so with u = (u_e, u_o)
+ * (even / odd l) A = [[D_e, T_eo], [T_oe, D_o]] with D_e, D_o diagonal and,
+ * when no axis is Neumann, T_oe = -T_eo^T (the transport part is skew,
+ * section "Discretized Radiative Transfer Equation").  The inner solve then
+ * runs conjugate gradients with a Jacobi preconditioner on the symmetric
+ * positive definite Schur complement S = D_e - T_eo D_o^-1 T_oe for u_e
+ * (right-hand side r_e - T_eo D_o^-1 r_o) and recovers u_o = D_o^-1 (r_o -
+ * T_oe u_e); its residual equals that of the whole system, and the inner stop
+ * tests it against inner_tol times the refinement residual.  One iteration
+ * applies A once (odd rows from the even part, then even rows), where CG on
+ * the normal equations applies A and A^T.  PN_ERR_ARG with a Neumann axis, with
+ * zero extinction in some cell (D_o singular: raise sigma_t_min) or PN_FP64.
+ * CGLS: the residual-based CGLS
  * form (r <- r - alpha q fused into s = A^T r).  CG: CG on the normal
  * equations A^T A u = A^T Q with the recursive normal residual
  * (s <- s - alpha A^T q, ||r||^2 <- ||r||^2 - alpha gamma; 10 vector passes
@@ -134,13 +148,15 @@ typedef struct {
  * every transport neighbour present, formed from the medium inside the
  * kernels: no extra memory traffic); the inner stop then tests the W-weighted
  * residual.  Needs the register-window stencil (PN_ERR_ARG with pn_set_tiles
- * or PN_FP64).  AUTO: CG_EQ on the register-window stencil, CG on the
- * LDS-tiled one.  The FP64 refinement checks the true, unweighted residual
+ * or PN_FP64).  AUTO: SCHUR on the register-window stencil (CG_EQ when an
+ * axis is Neumann or some cell has zero extinction), CG on the LDS-tiled one; the batched solve treats AUTO as
+ * CG_EQ.  The FP64 refinement checks the true, unweighted residual
  * ||Q - A x|| in every case. */
 #define PN_VARIANT_AUTO 0
 #define PN_VARIANT_CGLS 1
 #define PN_VARIANT_CG 2
 #define PN_VARIANT_CG_EQ 3
+#define PN_VARIANT_SCHUR 4
 
 #define PN_MAX_HISTORY 64
 /* Phases of a solve timed in pn_solve_info.t_ms (wall milliseconds, host
@@ -207,6 +223,16 @@ pn_status pn_layout_query(const pn_ctx* ctx, pn_layout* layout);
  * FP32 vectors of n_unknowns entries and must not overlap.  Asynchronous. */
 pn_status pn_apply(pn_ctx* ctx, const float* x, float* y, int transpose);
 
+/* The operator of the even-parity solve (PN_VARIANT_SCHUR) in FP32, with
+ * A = [[D_e, T_eo], [T_oe, D_o]] split by band parity (even / odd l):
+ *   y_o = -D_o^-1 T_oe x_e,   y_e = D_e x_e + T_eo y_o = S x_e,
+ * S = D_e - T_eo D_o^-1 T_oe the Schur complement of the even bands.  Reads
+ * only the even-band entries of x (packed layout, n_unknowns entries) and
+ * writes every entry of y.  These are the two stencil passes of one PCG
+ * iteration.  PN_ERR_ARG with a Neumann axis (there T_oe != -T_eo^T and the
+ * solve does not use S).  Asynchronous on the context stream. */
+pn_status pn_apply_schur(pn_ctx* ctx, const float* x, float* y);
+
 /* Row weights of the equilibrated CG variant (PN_VARIANT_CG_EQ): w[i] =
  * 1 / (d_i^2 + sum of the squared transport entries of row i with every
  * neighbour present), d_i the diagonal -- 1 / ||row i of A||_2^2 away from
@@ -261,6 +287,16 @@ pn_status pn_bench_apply(pn_ctx* ctx, int iters, int transpose, double* ms_per_a
 #define PN_KERNEL_APPLY_EQ 2
 #define PN_KERNEL_SUPD 3
 #define PN_KERNEL_UPDATE 4
+/* The kernels of the even-parity loop (PN_VARIANT_SCHUR), timed inside its
+ * own kernel sequence:
+ *   PN_KERNEL_ODD_W      w_o = -D_o^-1 T_oe p_e (odd rows)
+ *   PN_KERNEL_EVEN_S     q_e = D_e p_e + T_eo w_o with the FP64 partials of <p, q>
+ *   PN_KERNEL_PCG_XR     x += alpha p, r -= alpha q with <r, M r>, <r, r>
+ *   PN_KERNEL_PCG_P      p = M r + beta p */
+#define PN_KERNEL_ODD_W 5
+#define PN_KERNEL_EVEN_S 6
+#define PN_KERNEL_PCG_XR 7
+#define PN_KERNEL_PCG_P 8
 pn_status pn_bench_kernel(pn_ctx* ctx, int kernel, int iters, double* ms);
 
 /* Launch tuning: planes of z handled per thread block in the stencil apply

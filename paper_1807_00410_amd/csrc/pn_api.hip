@@ -132,6 +132,7 @@ void set_geometry(pn_ctx* c, int zchunk) {
   c->cplane = c->CX * (c->ny + 2);
   c->cs = (((long long)c->plane * (c->Ez + 2)) + 63) / 64 * 64;
   c->nv = c->cs * c->nc;
+  c->even.cs = c->cs;
   c->ncb = (c->Ex * c->Ey + kBlock - 1) / kBlock;
   if (zchunk <= 0) {
     // aim at ~2048 blocks (8 per CU), at least 4 planes per chunk
@@ -172,6 +173,7 @@ static void free_all(pn_ctx* c) {
   if (c->gexec32) hipGraphExecDestroy(c->gexec32);
   if (c->gexec64) hipGraphExecDestroy(c->gexec64);
   if (c->gexec_cg) hipGraphExecDestroy(c->gexec_cg);
+  if (c->gexec_schur) hipGraphExecDestroy(c->gexec_schur);
   hipFree(c->med); hipFree(c->med32);
   for (int i = 0; i < 2; ++i) { hipFree(c->r32[i]); hipFree(c->r64[i]); }
   hipFree(c->s32); hipFree(c->p32); hipFree(c->q32); hipFree(c->d32); hipFree(c->b32); hipFree(c->x64);
@@ -299,6 +301,7 @@ extern "C" pn_status pn_autotune(pn_ctx* c, int iters, int* zchunk, double* ms) 
   if (c->gexec32) { hipGraphExecDestroy(c->gexec32); c->gexec32 = nullptr; c->giters32 = 0; }
   if (c->gexec64) { hipGraphExecDestroy(c->gexec64); c->gexec64 = nullptr; c->giters64 = 0; }
   if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
+  if (c->gexec_schur) { hipGraphExecDestroy(c->gexec_schur); c->gexec_schur = nullptr; c->giters_schur = 0; }
   if (zchunk) *zchunk = z;
   if (ms) *ms = bms;
   return PN_OK;
@@ -401,6 +404,12 @@ pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* 
     if (n >= (1L << 31) - 1) { delete c; return fail(nullptr, PN_ERR_ARG, "too many unknowns (>= 2^31)"); }
   }
   c->n = n;
+  c->even.nk = 0;
+  for (int k = 0; k < c->nc; ++k) {
+    int l = 0;
+    while ((l + 1) * (l + 1) <= k) ++l;
+    if ((l & 1) == 0) c->even.k[c->even.nk++] = k;
+  }
   set_geometry(c, 0);
   c->max_blocks = 1 << 16;
   if (c->nblocks > c->max_blocks) { delete c; return fail(nullptr, PN_ERR_ARG, "grid too large in x*y"); }
@@ -449,7 +458,8 @@ pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* 
   SETUP_HIP(hipGetLastError());
   SETUP_HIP(hipMemcpyAsync(c->flag_host, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   SETUP_HIP(hipStreamSynchronize(c->stream));
-  if (*c->flag_host) return bail(PN_ERR_NONFINITE, "medium contains NaN or Inf");
+  if (*c->flag_host & 1) return bail(PN_ERR_NONFINITE, "medium contains NaN or Inf");
+  c->zero_ext = (*c->flag_host & 2) != 0;
   {
     // LDS per block: 64 KiB by default; up to the device's opt-in limit when
     // the kernel attribute can be raised.
@@ -494,6 +504,7 @@ extern "C" pn_status pn_set_zchunk(pn_ctx* c, int zchunk) {
   if (c->gexec32) { hipGraphExecDestroy(c->gexec32); c->gexec32 = nullptr; c->giters32 = 0; }
   if (c->gexec64) { hipGraphExecDestroy(c->gexec64); c->gexec64 = nullptr; c->giters64 = 0; }
   if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
+  if (c->gexec_schur) { hipGraphExecDestroy(c->gexec_schur); c->gexec_schur = nullptr; c->giters_schur = 0; }
   return PN_OK;
 }
 
@@ -501,6 +512,7 @@ extern "C" pn_status pn_set_tiles(pn_ctx* c, int tx, int ty, int zchunk) {
   if (!c) return PN_ERR_ARG;
   if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
+  if (c->gexec_schur) { hipGraphExecDestroy(c->gexec_schur); c->gexec_schur = nullptr; c->giters_schur = 0; }
   if (tx == 0 && ty == 0) {  // back to the register-window stencil
     c->use_lds = 0;
     return PN_OK;
@@ -563,6 +575,32 @@ extern "C" pn_status pn_apply(pn_ctx* c, const float* x, float* y, int transpose
   if (c->use_lds) PN_HIP(launch_lds(c, M_APPLY, false, a, c->stream));
   else PN_HIP((launch_stencil<float, M_APPLY, float>(c, a, c->stream)));
   PN_HIP((launch_pack<float, float, 1>(c, c->q32, y, c->stream)));
+  return PN_OK;
+}
+
+static bool schur_ok(const pn_ctx* c);
+
+extern "C" pn_status pn_apply_schur(pn_ctx* c, const float* x, float* y) {
+  if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
+  if (!x || !y) return fail(c, PN_ERR_ARG, "x or y is NULL");
+  if ((const void*)x == (const void*)y) return fail(c, PN_ERR_ARG, "x and y must not alias");
+  if (!schur_ok(c)) return fail(c, PN_ERR_ARG, "the even-parity operator needs T_oe = -T_eo^T (no Neumann axis) and positive extinction in every cell");
+  PN_HIP((launch_pack<float, float, 0>(c, x, c->p32, c->stream)));
+  StencilArgs a = base_args(c);
+  a.x = c->p32; a.y = c->p32;  // odd slots of p32 <- -D_o^-1 T_oe x_e
+  PN_HIP((launch_stencil<float, M_ODD_W, float>(c, a, c->stream)));
+  a.partials = c->partials; a.x = c->p32; a.y = c->q32;
+  PN_HIP((launch_stencil<float, M_EVEN_S, float>(c, a, c->stream)));
+  // y: even bands from q32, odd bands from p32
+  PN_HIP((launch_pack<float, float, 1>(c, c->q32, y, c->stream)));
+  PackArgs pa = pack_args(c);
+  for (int k = 0; k < c->nc; ++k) {
+    int l = 0;
+    while ((l + 1) * (l + 1) <= k) ++l;
+    if ((l & 1) == 0) pa.ex[k] = 0;  // even bands: keep what came from q32
+  }
+  PN_HIP((launch_pack_args<float, float, 1>(c, pa, c->p32, y, c->stream)));
   return PN_OK;
 }
 
@@ -632,8 +670,10 @@ extern "C" pn_status pn_bench_apply(pn_ctx* c, int iters, int transpose, double*
 // sees in a solve; events around the requested kernel give its mean time.
 // The device scalars are reset first (alpha = beta = 0.5, no stop flag); the
 // next solve re-initialises them.
+static int pcg_vec_blocks(const pn_ctx* c);
+
 extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* ms) {
-  if (!c || iters < 1 || !ms || kernel < PN_KERNEL_APPLY || kernel > PN_KERNEL_UPDATE)
+  if (!c || iters < 1 || !ms || kernel < PN_KERNEL_APPLY || kernel > PN_KERNEL_PCG_P)
     return c ? fail(c, PN_ERR_ARG, "bad arguments") : PN_ERR_ARG;
   if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (c->use_lds && kernel != PN_KERNEL_APPLY && kernel != PN_KERNEL_APPLY_T)
@@ -663,6 +703,23 @@ extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* m
         a.st = c->st; a.partials = c->partials; a.tsign = -1.0;
         a.x = c->q32; a.y = c->s32;
         return launch_stencil<float, M_SUPD, float>(c, a, c->stream);
+      case PN_KERNEL_ODD_W:
+        a.st = c->st; a.x = c->p32; a.y = c->p32;
+        return launch_stencil<float, M_ODD_W, float>(c, a, c->stream);
+      case PN_KERNEL_EVEN_S:
+        a.st = c->st; a.partials = c->partials; a.x = c->p32; a.y = c->q32;
+        return launch_stencil<float, M_EVEN_S, float>(c, a, c->stream);
+      case PN_KERNEL_PCG_XR:
+      case PN_KERNEL_PCG_P: {
+        const dim3 vg(pcg_vec_blocks(c), c->even.nk);
+        if (k == PN_KERNEL_PCG_XR)
+          hipLaunchKernelGGL(k_pcg_vec<1>, vg, dim3(kBlock), 0, c->stream, c->d32, c->r32[1], c->p32,
+                             (const float*)c->q32, (const float*)c->s32, c->even, c->partials, (const DevState*)c->st);
+        else
+          hipLaunchKernelGGL(k_pcg_vec<2>, vg, dim3(kBlock), 0, c->stream, c->d32, c->r32[1], c->p32,
+                             (const float*)c->q32, (const float*)c->s32, c->even, c->partials, (const DevState*)c->st);
+        return hipGetLastError();
+      }
       default:
         hipLaunchKernelGGL((k_update_xp<float>), dim3(stream_grid(c->nv / 4)), dim3(kBlock), 0, c->stream, c->d32,
                            c->p32, (const float*)c->s32, (long)c->nv, (const DevState*)c->st);
@@ -680,9 +737,12 @@ extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* m
     PN_HIP(hipEventElapsedTime(&t, e0, e1));
     total = t;
   } else {
-    const int seq[3] = {PN_KERNEL_APPLY_EQ, PN_KERNEL_SUPD, PN_KERNEL_UPDATE};
+    const int seq_cg[3] = {PN_KERNEL_APPLY_EQ, PN_KERNEL_SUPD, PN_KERNEL_UPDATE};
+    const int seq_schur[4] = {PN_KERNEL_ODD_W, PN_KERNEL_EVEN_S, PN_KERNEL_PCG_XR, PN_KERNEL_PCG_P};
+    const bool sc = kernel >= PN_KERNEL_ODD_W;
     for (int i = 0; i <= iters; ++i) {  // iteration 0 warms up
-      for (int k : seq) {
+      for (int j = 0; j < (sc ? 4 : 3); ++j) {
+        const int k = sc ? seq_schur[j] : seq_cg[j];
         if (k == kernel) PN_HIP(hipEventRecord(e0, c->stream));
         PN_HIP(launch(k));
         if (k == kernel) PN_HIP(hipEventRecord(e1, c->stream));
@@ -771,6 +831,60 @@ static hipError_t enqueue_iteration_cg(pn_ctx* c, float* d, float* p, float* q, 
   hipLaunchKernelGGL((k_update_xp<float>), dim3(stream_grid(c->nv / 4)), dim3(kBlock), 0, st, d, p,
                      (const float*)s, (long)c->nv, (const DevState*)c->st);
   return hipGetLastError();
+}
+
+// Even-parity PCG (Schur complement S = D_e - T_eo D_o^-1 T_oe, Jacobi
+// preconditioner m = 1 / diag(S) in the even slots of s32; PCG vectors in the
+// even slots: x = d32, r = r32[1], p = p32, q = q32):
+// w_o = -D_o^-1 T_oe p_e (odd slots of p) | q_e = S p_e | alpha | x, r update |
+// beta | p = m r + beta p.
+static int pcg_vec_blocks(const pn_ctx* c) {
+  const long long n4 = c->cs / 4;
+  const long long b = (n4 + kBlock - 1) / kBlock;
+  return (int)std::max<long long>(1, std::min<long long>(b, 256));
+}
+
+static hipError_t enqueue_iteration_schur(pn_ctx* c, hipStream_t st) {
+  StencilArgs a = base_args(c);
+  a.st = c->st;
+  a.tsign = 1.0;
+  a.x = c->p32; a.y = c->p32;
+  hipError_t e = launch_stencil<float, M_ODD_W, float>(c, a, st);
+  if (e != hipSuccess) return e;
+  a.partials = c->partials;
+  a.x = c->p32; a.y = c->q32;
+  e = launch_stencil<float, M_EVEN_S, float>(c, a, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fin_alpha_pcg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->nblocks);
+  const dim3 vg(pcg_vec_blocks(c), c->even.nk);
+  hipLaunchKernelGGL(k_pcg_vec<1>, vg, dim3(kBlock), 0, st, c->d32, c->r32[1], c->p32, (const float*)c->q32,
+                     (const float*)c->s32, c->even, c->partials, (const DevState*)c->st);
+  hipLaunchKernelGGL(k_fin_beta_pcg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, (int)(vg.x * vg.y));
+  hipLaunchKernelGGL(k_pcg_vec<2>, vg, dim3(kBlock), 0, st, c->d32, c->r32[1], c->p32, (const float*)c->q32,
+                     (const float*)c->s32, c->even, c->partials, (const DevState*)c->st);
+  return hipGetLastError();
+}
+
+static pn_status build_graph_schur(pn_ctx* c, int iters, hipGraphExec_t* exec) {
+  hipGraph_t g = nullptr;
+  PN_HIP(hipStreamBeginCapture(c->sstream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < iters && e == hipSuccess; ++i) e = enqueue_iteration_schur(c, c->sstream);
+  hipError_t e2 = hipStreamEndCapture(c->sstream, &g);
+  if (e != hipSuccess) { if (g) hipGraphDestroy(g); return fail(c, PN_ERR_HIP, std::string("capture: ") + hipGetErrorString(e)); }
+  if (e2 != hipSuccess) return fail(c, PN_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
+  hipError_t e3 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e3 != hipSuccess) return fail(c, PN_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e3));
+  return PN_OK;
+}
+
+// True when A = [[D_e, T_eo], [T_oe, D_o]] has T_oe = -T_eo^T (no Neumann
+// axis) and D_o is invertible (positive extinction everywhere: sigma_t -
+// g^l sigma_s > 0 for odd l), so that the even-parity Schur complement
+// exists and is symmetric positive definite.
+static bool schur_ok(const pn_ctx* c) {
+  return c->bcs[0] != BC_NEUMANN && c->bcs[1] != BC_NEUMANN && c->bcs[2] != BC_NEUMANN && !c->zero_ext;
 }
 
 static pn_status build_graph_cg(pn_ctx* c, int iters, bool eq, hipGraphExec_t* exec) {
@@ -982,20 +1096,42 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
   // residual (10 vector passes per iteration, the A^T pass streams one
   // vector); otherwise CGLS with the recursive residual r (11 passes, r
   // ping-pong, the A^T pass streams two).
-  const bool cg = (sizeof(T) == 4) && o.variant != PN_VARIANT_CGLS;
+  // FP32 even-parity PCG (Schur complement): SCHUR, and AUTO on the
+  // register-window stencil when no axis is Neumann
+  const bool schur = (sizeof(T) == 4) && schur_ok(c) &&
+                     (o.variant == PN_VARIANT_SCHUR || (o.variant == PN_VARIANT_AUTO && !c->use_lds));
+  const bool cg = (sizeof(T) == 4) && !schur && o.variant != PN_VARIANT_CGLS;
   // row equilibration: AUTO and CG_EQ on the register-window stencil
   const bool eq = cg && !c->use_lds && (o.variant == PN_VARIANT_AUTO || o.variant == PN_VARIANT_CG_EQ);
   if (cg) {
     gexec = &c->gexec_cg;
     giters = &c->giters_cg;
   }
+  if (schur) {
+    gexec = &c->gexec_schur;
+    giters = &c->giters_schur;
+  }
   int gi = o.graph_iters < 2 ? 2 : (o.graph_iters + 1) & ~1;  // even: r ends in r0
   if (*gexec == nullptr || *giters != gi || (cg && c->gcg_eq != (int)eq)) {
     if (*gexec) { hipGraphExecDestroy(*gexec); *gexec = nullptr; }
-    pn_status e = cg ? build_graph_cg(c, gi, eq, gexec) : build_graph<T>(c, gi, d, p, q, s, r0, r1, gexec);
+    pn_status e = schur ? build_graph_schur(c, gi, gexec)
+                  : cg  ? build_graph_cg(c, gi, eq, gexec)
+                        : build_graph<T>(c, gi, d, p, q, s, r0, r1, gexec);
     if (e != PN_OK) return e;
     *giters = gi;
     if (cg) c->gcg_eq = (int)eq;
+  }
+  const dim3 vg(pcg_vec_blocks(c), c->even.nk);
+  if (schur) {
+    // Jacobi preconditioner: 1 / d_o in the odd slots of q32 (d32 = 0, x2 =
+    // NULL reads as 1), then m = 1 / diag(S) in the even slots of s32
+    hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(c->nv)), dim3(kBlock), 0, c->sstream, c->d32, (long)c->nv, 0.f);
+    PN_HIP(hipGetLastError());
+    StencilArgs a = base_args(c);
+    a.x = c->d32; a.x2 = nullptr; a.y = c->q32;
+    PN_HIP((launch_stencil<float, M_ODD_BACK, float>(c, a, c->sstream)));
+    a.x = c->q32; a.y = c->s32;
+    PN_HIP((launch_stencil<float, M_EVEN_JAC, float>(c, a, c->sstream)));
   }
   hipStream_t ss = c->sstream;
   DevState init;
@@ -1083,6 +1219,35 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, d, (long)c->nv, T(0));
     StencilArgs a = base_args(c);
     a.partials = c->partials;
+    if constexpr (sizeof(T) == 4) {
+      if (schur) {
+        // reduced right-hand side f = r0_e - T_eo D_o^-1 r0_o (u_o = D_o^-1 r0_o
+        // in the odd slots of q32, f in the even slots of r32[1])
+        StencilArgs b = base_args(c);
+        b.x = d; b.x2 = r0; b.y = q;
+        PN_HIP((launch_stencil<float, M_ODD_BACK, float>(c, b, ss)));
+        b.x = q; b.x2 = r0; b.y = r1;
+        PN_HIP((launch_stencil<float, M_EVEN_RHS, float>(c, b, ss)));
+        hipLaunchKernelGGL(k_pcg_vec<0>, vg, dim3(kBlock), 0, ss, d, r1, p, (const float*)q, (const float*)s,
+                           c->even, c->partials, (const DevState*)c->st);
+        hipLaunchKernelGGL(k_fin_init_pcg, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials, (int)(vg.x * vg.y),
+                           itol * itol);
+        PN_HIP(hipGetLastError());
+        for (;;) {
+          PN_HIP(hipGraphLaunch(*gexec, ss));
+          PN_HIP(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, ss));
+          PN_HIP(hipStreamSynchronize(ss));
+          if (c->st_host->done || c->st_host->stop) break;
+        }
+        // odd part: d_o = (r0_o - T_oe d_e) / d_o
+        b.x = d; b.x2 = r0; b.y = d;
+        PN_HIP((launch_stencil<float, M_ODD_BACK, float>(c, b, ss)));
+        hipLaunchKernelGGL((k_axpy64<T>), dim3(grid_for(c->nv)), dim3(kBlock), 0, ss, c->x64, (const T*)d, (long)c->nv);
+        PN_HIP(hipGetLastError());
+        t_kry += ms_since(tk);
+        continue;
+      }
+    }
     const T* rs = r0;
     if constexpr (sizeof(T) == 4) {
       if (eq) {  // r1 = W r0; the inner solve tracks <r, W r>
@@ -1119,7 +1284,7 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     info->t_ms[PN_PHASE_RESIDUAL] = t_res;
     info->t_ms[PN_PHASE_KRYLOV] = t_kry;
     info->t_ms[PN_PHASE_LEARNED] = t_net;
-    const SolveBytes sb = solve_bytes(c, sizeof(T) == 8, cg, eq);
+    const SolveBytes sb = schur ? schur_bytes(c) : solve_bytes(c, sizeof(T) == 8, cg, eq);
     info->bytes = sb.per_iter * info->inner_iters + sb.per_start * starts + sb.per_resid * outer;
     info->achieved_gbs = (t_res + t_kry) > 0.0 ? info->bytes / ((t_res + t_kry) * 1e6) : 0.0;
   }
@@ -1140,7 +1305,9 @@ extern "C" pn_status pn_solve(pn_ctx* c, const float* rhs, double* x, double tol
   if (o.precision != PN_FP32_IR && o.precision != PN_FP64) return fail(c, PN_ERR_ARG, "unknown precision");
   if (o.learned < PN_LEARNED_OFF || o.learned > PN_LEARNED_GUESS_CORRECT)
     return fail(c, PN_ERR_ARG, "unknown learned mode");
-  if (o.variant < PN_VARIANT_AUTO || o.variant > PN_VARIANT_CG_EQ) return fail(c, PN_ERR_ARG, "unknown variant");
+  if (o.variant < PN_VARIANT_AUTO || o.variant > PN_VARIANT_SCHUR) return fail(c, PN_ERR_ARG, "unknown variant");
+  if (o.variant == PN_VARIANT_SCHUR && (!schur_ok(c) || o.precision != PN_FP32_IR))
+    return fail(c, PN_ERR_ARG, "the even-parity Schur variant needs FP32_IR, no Neumann axis and positive extinction");
   if (o.variant == PN_VARIANT_CG_EQ && (c->use_lds || o.precision != PN_FP32_IR))
     return fail(c, PN_ERR_ARG, "the equilibrated CG variant needs FP32_IR and the register-window stencil");
   if (info) std::memset(info, 0, sizeof(*info));

@@ -48,6 +48,7 @@ struct pn_ctx {
   int order = 0, nc = 0;
   int nx = 0, ny = 0, nz = 0, bc = 0;
   int bcs[3] = {0, 0, 0};  // boundary type per axis (BC_VACUUM / BC_PERIODIC / BC_NEUMANN)
+  bool zero_ext = false;   // some cell has zero extinction after the threshold (D_o singular)
   double h = 0.0;
   float g = 0.f, thr = 0.f;
   hipStream_t stream = nullptr;   // caller's stream
@@ -86,6 +87,9 @@ struct pn_ctx {
   int use_lds = 0;  // applies and the CG variant use it (opt-in, pn_set_tiles)
   int TX = 0, TY = 0, ntx = 0, nty = 0, lzchunk = 0, lnzc = 0, lnblocks = 0;
   size_t lds_bytes = 0, lds_max = 0;
+  hipGraphExec_t gexec_schur = nullptr;  // captured even-parity PCG iterations
+  int giters_schur = 0;
+  EvenSlots even{};                   // even-band coefficient arrays of the padded vectors
   hipGraphExec_t gexec_cg = nullptr;  // captured CG-on-normal-equations iterations
   int giters_cg = 0;
   int gcg_eq = 0;                     // gexec_cg holds the row-equilibrated form
@@ -136,6 +140,23 @@ inline SolveBytes solve_bytes(const pn_ctx* c, bool fp64, bool cg, bool eq) {
   return b;
 }
 
+// Even-parity PCG: per iteration the odd rows (read the even vector, write the
+// odd one), the even rows (read both, write the even one), x/r (5 even reads,
+// 2 writes), p (3 reads, 1 write); the medium per stencil pass.
+inline SolveBytes schur_bytes(const pn_ctx* c) {
+  double ne = 0.0;
+  for (int j = 0; j < c->even.nk; ++j) {
+    const int k = c->even.k[j];
+    ne += (double)c->ext[k][0] * c->ext[k][1] * c->ext[k][2];
+  }
+  const double n = (double)c->n, no = n - ne, cells = (double)c->nx * c->ny * c->nz;
+  SolveBytes b;
+  b.per_iter = (ne + no) * 4.0 + (n + ne) * 4.0 + 7.0 * ne * 4.0 + 4.0 * ne * 4.0 + 16.0 * cells;
+  b.per_start = 3.0 * n * 4.0 + 4.0 * ne * 4.0 + 16.0 * cells + (ne + n) * 4.0 + 12.0 * n;
+  b.per_resid = 16.0 * n + 8.0 * cells;
+  return b;
+}
+
 // Context with geometry and medium; the Krylov workspace only if `workspace`.
 pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* stream, bool workspace,
                     pn_ctx** out);
@@ -158,9 +179,11 @@ inline PackArgs pack_args(const pn_ctx* c) {
 }
 
 
-// DIR 0: padded <- packed; 1: packed <- padded; 2: packed += padded
+// DIR 0: padded <- packed; 1: packed <- padded; 2: packed += padded.
+// launch_pack_args converts the coefficients of `pa` (a coefficient with
+// ex = 0 is skipped).
 template <typename TS, typename TD, int DIR>
-inline hipError_t launch_pack(const pn_ctx* c, const TS* src, TD* dst, hipStream_t s) {
+inline hipError_t launch_pack_args(const pn_ctx* c, const PackArgs& pa, const TS* src, TD* dst, hipStream_t s) {
   long long maxsz = 0;
   for (int k = 0; k < c->nc; ++k) {
     long long sz = (long long)c->ext[k][0] * c->ext[k][1] * c->ext[k][2];
@@ -168,8 +191,12 @@ inline hipError_t launch_pack(const pn_ctx* c, const TS* src, TD* dst, hipStream
   }
   long long bx = (maxsz + kBlock - 1) / kBlock;
   if (bx > 1024) bx = 1024;
-  hipLaunchKernelGGL((k_pack<TS, TD, DIR>), dim3((unsigned)bx, c->nc), dim3(kBlock), 0, s, src, dst, pack_args(c));
+  hipLaunchKernelGGL((k_pack<TS, TD, DIR>), dim3((unsigned)bx, c->nc), dim3(kBlock), 0, s, src, dst, pa);
   return hipGetLastError();
+}
+template <typename TS, typename TD, int DIR>
+inline hipError_t launch_pack(const pn_ctx* c, const TS* src, TD* dst, hipStream_t s) {
+  return launch_pack_args<TS, TD, DIR>(c, pack_args(c), src, dst, s);
 }
 
 
@@ -185,7 +212,12 @@ inline hipError_t launch_stencil(const pn_ctx* c, const StencilArgs& a, hipStrea
     kind = (MODE == M_APPLY) ? K_F32_APPLY
          : (MODE == M_SUPD) ? K_F32_SUPD
          : (MODE == M_APPLY_EQ) ? K_F32_APPLY_EQ
-         : (MODE == M_EQS) ? K_F32_EQS : K_F32_TRANSR;
+         : (MODE == M_EQS) ? K_F32_EQS
+         : (MODE == M_ODD_W) ? K_F32_ODD_W
+         : (MODE == M_EVEN_S) ? K_F32_EVEN_S
+         : (MODE == M_EVEN_RHS) ? K_F32_EVEN_RHS
+         : (MODE == M_ODD_BACK) ? K_F32_ODD_BACK
+         : (MODE == M_EVEN_JAC) ? K_F32_EVEN_JAC : K_F32_TRANSR;
   else if constexpr (MODE == M_APPLY) kind = K_F64_APPLY;
   else if constexpr (MODE == M_TRANSR) kind = K_F64_TRANSR;
   else kind = (sizeof(TO) == 4) ? K_F64_RESID32 : K_F64_RESID64;

@@ -60,7 +60,22 @@ struct DevState {
 // M_SUPD: s <- s - alpha * op(x) (the normal-equation residual update of CG
 // on A^T A).  M_APPLY_EQ / M_EQS: the row-equilibrated forms (w = 1 / ||row
 // of A||^2 per unknown, formed from the medium in the kernel).
-enum Mode { M_APPLY = 0, M_TRANSR = 1, M_RESID = 2, M_SUPD = 3, M_APPLY_EQ = 4, M_EQS = 5 };
+enum Mode {
+  M_APPLY = 0, M_TRANSR = 1, M_RESID = 2, M_SUPD = 3, M_APPLY_EQ = 4, M_EQS = 5,
+  // even-parity (Schur complement) solve, rows of one band parity only
+  M_ODD_W = 6, M_EVEN_S = 7, M_EVEN_RHS = 8, M_ODD_BACK = 9, M_EVEN_JAC = 10
+};
+
+// Band parity of the rows a mode computes: 0 all, 1 even l, 2 odd l.  The
+// band parity of a coefficient is the parity of its staggering class
+// (px + py + pz): even bands sit at cell centres and edges, odd ones on faces
+// and corners, and the transport couples only bands l and l +- 1, so A is
+// [[D_e, T_eo], [T_oe, D_o]] with D_e, D_o diagonal (and T_oe = -T_eo^T when
+// no axis is Neumann).
+constexpr int mode_rows(int m) {
+  return (m == M_EVEN_S || m == M_EVEN_RHS || m == M_EVEN_JAC) ? 1 : (m == M_ODD_W || m == M_ODD_BACK) ? 2 : 0;
+}
+constexpr int class_parity(int c) { return ((c & 1) + ((c >> 1) & 1) + ((c >> 2) & 1)) & 1; }
 
 // Internal vectors live on a padded lattice shared by every coefficient:
 // coefficient k occupies [k*cs, (k+1)*cs); lattice point (x, y, z) of any
@@ -177,6 +192,15 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 //   M_SUPD   y = y - alpha op(x)               [||y||^2]
 //   M_APPLY_EQ  y = W A x                      [<A x, W A x>]
 //   M_EQS    y = W x                           [<x, W x>]
+// Even-parity Schur complement S = D_e - T_eo D_o^-1 T_oe (rows of one band
+// parity; T the transport part of A, (T x) on those rows reads only the other
+// parity of x):
+//   M_ODD_W    y_o = -(T x)_o / d_o            (x even: p_e)
+//   M_EVEN_S   y_e = d_e x_e + (T x)_e         [<x_e, y_e>]  (x odd: w_o)
+//   M_EVEN_RHS y_e = x2_e - (T x)_e            (x odd: D_o^-1 r_o; x2: r)
+//   M_ODD_BACK y_o = (x2_o - (T x)_o) / d_o    (x even: d_e; x2: r)
+//   M_EVEN_JAC y_e = 1 / (d_e + sum over the row's transport entries (T)_ij^2 x_j)
+//              (x odd: 1 / d_o): the inverse diagonal of S
 // W is diagonal: w = 1 / (d^2 + sum of the squared transport entries of the
 // row), d the row's diagonal -- the inverse squared 2-norm of the row of A
 // away from the boundary.
@@ -288,14 +312,23 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
   };
 
   double nrm0 = 0.0, nrm1 = 0.0;
+  // coefficients whose window is kept: every one, or for the one-parity
+  // modes the other parity (their transport inputs) and, for M_EVEN_S, the
+  // rows' own values
+  constexpr int kRows = mode_rows(MODE);
+  constexpr auto in_window = [](int K) constexpr {
+    return kRows == 0 || class_parity(cls_id(K)) != kRows - 1 || MODE == M_EVEN_S;
+  };
   {  // lanes past the last column recompute column 0 and store nothing
     T cur[NC], nb[NC];
     {
       const long long zo0 = zoff(z0), zom = zoff(z0 - 1);
       sfor<NC>([&](auto KPc) {
         constexpr int KP = decltype(KPc)::value;
-        if constexpr (cls_z(KP) == 1) nb[KP] = load(KPc, zo0, o);
-        else cur[KP] = load(KPc, zom, o);
+        if constexpr (in_window(KP)) {
+          if constexpr (cls_z(KP) == 1) nb[KP] = load(KPc, zo0, o);
+          else cur[KP] = load(KPc, zom, o);
+        }
       });
     }
     T msa[8], mss[8];  // cells of the plane below (0..3) and of this plane (4..7)
@@ -306,8 +339,10 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
       const long long zo = zoff(z), zon = zoff(z + 1);
       sfor<NC>([&](auto KPc) {
         constexpr int KP = decltype(KPc)::value;
-        if constexpr (cls_z(KP) == 1) { cur[KP] = nb[KP]; nb[KP] = load(KPc, zon, o); }
-        else { nb[KP] = cur[KP]; cur[KP] = load(KPc, zo, o); }
+        if constexpr (in_window(KP)) {
+          if constexpr (cls_z(KP) == 1) { cur[KP] = nb[KP]; nb[KP] = load(KPc, zon, o); }
+          else { nb[KP] = cur[KP]; cur[KP] = load(KPc, zo, o); }
+        }
       });
       cells(z, msa + 4, mss + 4);
       // Class means of sigma_a and sigma_s (cells visited z-major, lower
@@ -347,7 +382,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
       }
       sfor<8>([&](auto Cc) {
         constexpr int c = decltype(Cc)::value;
-        if constexpr (TB::class_has_rows(c)) {
+        if constexpr (TB::class_has_rows(c) && (kRows == 0 || class_parity(c) == kRows - 1)) {
 #ifdef PN_CLASS_BARRIER
           // keep each class group's loads from being hoisted above the previous
           // group (bounds the live registers)
@@ -376,7 +411,14 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
             constexpr bool first = TB::starts_difference(I);
             if constexpr (first) {
               constexpr int p = cls_axis(cp.kp, cp.d);
-              if constexpr (cp.d == 2) {
+              if constexpr (MODE == M_EVEN_JAC) {  // the two samples summed (squared couplings)
+                if constexpr (cp.d == 2) {
+                  dcur = nb[cp.kp] + cur[cp.kp];
+                } else {
+                  const unsigned lo = (cp.d == 0) ? (p ? oxp : oxm) : (p ? oyp : oym);
+                  dcur = load(std::integral_constant<int, cp.kp>{}, zo, lo) + cur[cp.kp];
+                }
+              } else if constexpr (cp.d == 2) {
                 if constexpr (GEN) dcur = p ? nhz * nb[cp.kp] - nlz * cur[cp.kp] : nbz * (cur[cp.kp] - nb[cp.kp]);
                 else dcur = p ? nb[cp.kp] - cur[cp.kp] : cur[cp.kp] - nb[cp.kp];
               } else {
@@ -390,7 +432,8 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
                 }
               }
             }
-            acc[cp.k] = fmadd<T>(T(cp.c), dcur, acc[cp.k]);
+            if constexpr (MODE == M_EVEN_JAC) acc[cp.k] = fmadd<T>(T(cp.c * cp.c), dcur, acc[cp.k]);
+            else acc[cp.k] = fmadd<T>(T(cp.c), dcur, acc[cp.k]);
           });
           constexpr int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
           const bool ok = act && (cx || okx0) && (cy || oky0) && (cz || okz0);
@@ -402,7 +445,13 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
               if constexpr (cls_id(K) == c) {
                 const long long base = cbase(K, zo);
                 const T dg = fmadd<T>(T(a.omg[band_of(K)]), css[c], csa[c]);
-                T out = fmadd<T>(tinvh, acc[K], dg * cur[K]);
+                T out;
+                if constexpr (MODE == M_ODD_W) out = -(tinvh * acc[K]) / dg;
+                else if constexpr (MODE == M_EVEN_RHS) out = T(ldb(X2 + base, o)) - tinvh * acc[K];
+                else if constexpr (MODE == M_ODD_BACK)  // x2 == NULL reads as 1 (then y_o = 1 / d_o for x = 0)
+                  out = ((X2 != nullptr ? T(ldb(X2 + base, o)) : T(1)) - tinvh * acc[K]) / dg;
+                else if constexpr (MODE == M_EVEN_JAC) out = T(1) / fmadd<T>(invh2, acc[K], dg);
+                else out = fmadd<T>(tinvh, acc[K], dg * cur[K]);
                 if constexpr (MODE == M_EQS) out = cur[K];
                 if constexpr (MODE == M_APPLY_EQ || MODE == M_EQS) {
                   constexpr T rc2 = T(TB::row_c2(K));
@@ -418,7 +467,8 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
                 }
                 if constexpr (MODE == M_SUPD) out = fmadd<T>(-alpha, out, yold[K]);
                 stb(Y + base, oo, TO(out));
-                if constexpr (NORM && MODE != M_APPLY_EQ && MODE != M_EQS) cn0 = fmadd<T>(out, out, cn0);
+                if constexpr (MODE == M_EVEN_S) cn0 = fmadd<T>(cur[K], out, cn0);
+                else if constexpr (NORM && MODE != M_APPLY_EQ && MODE != M_EQS) cn0 = fmadd<T>(out, out, cn0);
                 if constexpr (MODE == M_TRANSR) {
                   stb(Y2 + base, oo, TO(cur[K]));
                   cn1 = fmadd<T>(cur[K], cur[K], cn1);
@@ -447,7 +497,9 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
 template <int N, typename T, int MODE, typename TO, bool GEN, bool NORM>
 __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil(const StencilArgs a) {
   // In the Krylov loop the A p launch also ends once the stop flag is up.
-  if (a.st != nullptr && (a.st->done || ((MODE == M_APPLY || MODE == M_APPLY_EQ) && a.st->stop))) return;
+  if (a.st != nullptr &&
+      (a.st->done || ((MODE == M_APPLY || MODE == M_APPLY_EQ || MODE == M_ODD_W || MODE == M_EVEN_S) && a.st->stop)))
+    return;
   stencil_body<N, T, MODE, TO, GEN, NORM>(a, xcd_remap(blockIdx.x, a.nblocks));
 }
 
@@ -703,8 +755,9 @@ __global__ void __launch_bounds__(kBlock) k_axpy64(double* __restrict__ x, const
 
 // Padded cell arrays: med32 = (sigma_a, sigma_s) in FP32 and med = (sigma_t,
 // albedo) with sigma_t raised to the threshold; the one-cell halo holds
-// clamped (vacuum, Neumann) or wrapped (periodic) copies, per axis.  Flags
-// NaN / Inf.
+// clamped (vacuum, Neumann) or wrapped (periodic) copies, per axis.  Sets
+// bit 0 of *bad for NaN / Inf, bit 1 for a cell whose (thresholded)
+// extinction is not positive.
 static __global__ void __launch_bounds__(kBlock) k_medium_prep(const float* __restrict__ sigma_t,
                                                         const float* __restrict__ albedo, float thr,
                                                         int nx, int ny, int nz, int perx, int pery, int perz,
@@ -720,12 +773,13 @@ static __global__ void __launch_bounds__(kBlock) k_medium_prep(const float* __re
     pz = perz ? wrapi(pz, nz) : min(max(pz, 0), nz - 1);
     const long long src = ((long long)pz * ny + py) * nx + px;
     const float s = sigma_t[src], al = albedo[src];
-    if (!isfinite(s) || !isfinite(al)) b = 1;
+    if (!isfinite(s) || !isfinite(al)) b |= 1;
     const float st = fmaxf(s, thr);
+    if (!(st > 0.f)) b |= 2;
     med[i] = make_float2(st, al);
     med32[i] = make_float2(st * (1.0f - al), st * al);
   }
-  if (b) atomicOr(bad, 1);
+  if (b) atomicOr(bad, b);
 }
 
 // Layout conversion between the packed API layout (coefficient k contiguous
@@ -766,6 +820,133 @@ static __global__ void __launch_bounds__(kBlock) k_check_finite(const float* __r
   if (b) atomicOr(bad, 1);
 }
 
+
+// ------------------------------------------------- even-parity PCG (Schur) --
+// CG with a Jacobi preconditioner on S d_e = f, S = D_e - T_eo D_o^-1 T_oe
+// (symmetric positive definite when T_oe = -T_eo^T), on the even-band
+// coefficients of the padded vectors.  DevState: gamma = <r, M r>, rr = <r, r>,
+// qq = <p, S p>.  The reduced residual equals the residual of the whole system
+// once the odd part is back-substituted, so the inner stop tests <r, r>.
+__device__ __forceinline__ void fin_alpha_pcg(DevState* st, const double* partials, int n) {
+  if (st->done) return;
+  if (st->stop) {
+    if (threadIdx.x == 0) st->done = 1;
+    return;
+  }
+  double pq, unused;
+  grid_sum2(partials, n, pq, unused);
+  if (threadIdx.x == 0) {
+    st->qq = pq;
+    if (!(pq > 0.0) || !finite_d(pq)) {
+      st->breakdown = 1;
+      st->alpha = 0.0;
+      st->stop = 1;
+      st->done = 1;
+    } else {
+      st->alpha = st->gamma / pq;
+    }
+  }
+}
+
+__device__ __forceinline__ void fin_beta_pcg(DevState* st, const double* partials, int n) {
+  if (st->done || st->stop) return;
+  double rz, rr;
+  grid_sum2(partials, n, rz, rr);
+  if (threadIdx.x == 0) {
+    const double g0 = st->gamma;
+    st->beta = (g0 > 0.0) ? rz / g0 : 0.0;
+    st->gamma = rz;
+    st->rr = rr;
+    st->iters += 1;
+    if (!finite_d(rr) || !finite_d(rz)) { st->breakdown = 1; st->stop = 1; st->nonfinite = 1.0; }
+    if (rr <= st->tol2 || st->iters >= st->max_iters || !(rz > 0.0)) st->stop = 1;
+  }
+}
+
+// start of an inner solve: gamma = <r, M r>, rr = <r, r>; stop at rr <= itol2 * ||r0||^2
+__device__ __forceinline__ void fin_init_pcg(DevState* st, const double* partials, int n, double inner_tol2) {
+  double rz, rr;
+  grid_sum2(partials, n, rz, rr);
+  if (threadIdx.x == 0) {
+    st->gamma = rz;
+    st->rr = rr;
+    st->rr0 = st->rtrue2;
+    st->tol2 = inner_tol2 * st->rtrue2;
+    st->stop = (rz > 0.0 && finite_d(rz) && rr > st->tol2) ? 0 : 1;
+    st->done = 0;
+    st->breakdown = 0;
+    st->alpha = 0.0;
+    st->beta = 0.0;
+  }
+}
+
+static __global__ void __launch_bounds__(kBlock) k_fin_alpha_pcg(DevState* st, const double* partials, int n) { fin_alpha_pcg(st, partials, n); }
+static __global__ void __launch_bounds__(kBlock) k_fin_beta_pcg(DevState* st, const double* partials, int n) { fin_beta_pcg(st, partials, n); }
+static __global__ void __launch_bounds__(kBlock) k_fin_init_pcg(DevState* st, const double* partials, int n, double inner_tol2) { fin_init_pcg(st, partials, n, inner_tol2); }
+
+// The even-band coefficient arrays of a padded vector: array j of the list
+// starts at k[j] * cs; each is cs floats (a multiple of 64).  Grid: (blocks
+// per array, arrays); block partials in the order blockIdx.y * gridDim.x +
+// blockIdx.x.
+struct EvenSlots {
+  int nk;
+  int k[kMaxCoeff];
+  long long cs;
+};
+
+// OP 0 (init):    p = m r                        [<r, m r>, <r, r>]
+// OP 1 (x, r):    x += alpha p, r -= alpha q     [<r, m r>, <r, r>]
+// OP 2 (p):       p = m r + beta p
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_pcg_vec(float* __restrict__ x, float* __restrict__ r,
+                                                    float* __restrict__ p, const float* __restrict__ q,
+                                                    const float* __restrict__ m, const EvenSlots es,
+                                                    double* __restrict__ partials, const DevState* st) {
+  if (OP != 0 && st->done) return;
+  const long long base = (long long)es.k[blockIdx.y] * es.cs;
+  const long long n4 = es.cs >> 2;
+  const long long stride = (long long)gridDim.x * kBlock;
+  const float al = OP == 1 ? float(st->alpha) : 0.f, be = OP == 2 ? float(st->beta) : 0.f;
+  float4* x4 = reinterpret_cast<float4*>(x + base);
+  float4* r4 = reinterpret_cast<float4*>(r + base);
+  float4* p4 = reinterpret_cast<float4*>(p + base);
+  const float4* q4 = reinterpret_cast<const float4*>(q + base);
+  const float4* m4 = reinterpret_cast<const float4*>(m + base);
+  double s0 = 0.0, s1 = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride) {
+    float4 rv = ld_nt(r4 + i);
+    const float4 mv = ld_nt(m4 + i);
+    if constexpr (OP == 1) {
+      const float4 pv = ld_nt(p4 + i), qv = ld_nt(q4 + i);
+      float4 xv = ld_nt(x4 + i);
+      xv.x = __fmaf_rn(al, pv.x, xv.x); xv.y = __fmaf_rn(al, pv.y, xv.y);
+      xv.z = __fmaf_rn(al, pv.z, xv.z); xv.w = __fmaf_rn(al, pv.w, xv.w);
+      rv.x = __fmaf_rn(-al, qv.x, rv.x); rv.y = __fmaf_rn(-al, qv.y, rv.y);
+      rv.z = __fmaf_rn(-al, qv.z, rv.z); rv.w = __fmaf_rn(-al, qv.w, rv.w);
+      st_nt(x4 + i, xv);
+      st_nt(r4 + i, rv);
+    }
+    if constexpr (OP == 2) {
+      float4 pv = ld_nt(p4 + i);
+      pv.x = __fmaf_rn(be, pv.x, mv.x * rv.x); pv.y = __fmaf_rn(be, pv.y, mv.y * rv.y);
+      pv.z = __fmaf_rn(be, pv.z, mv.z * rv.z); pv.w = __fmaf_rn(be, pv.w, mv.w * rv.w);
+      st_nt(p4 + i, pv);
+    } else {
+      const float4 z = make_float4(mv.x * rv.x, mv.y * rv.y, mv.z * rv.z, mv.w * rv.w);
+      if constexpr (OP == 0) st_nt(p4 + i, z);
+      s0 += double(fmadd<float>(z.x, rv.x, fmadd<float>(z.y, rv.y, fmadd<float>(z.z, rv.z, z.w * rv.w))));
+      s1 += double(fmadd<float>(rv.x, rv.x, fmadd<float>(rv.y, rv.y, fmadd<float>(rv.z, rv.z, rv.w * rv.w))));
+    }
+  }
+  if constexpr (OP != 2) {
+    block_sum2(s0, s1);
+    if (threadIdx.x == 0) {
+      const int b = blockIdx.y * gridDim.x + blockIdx.x;
+      partials[2 * b] = s0;
+      partials[2 * b + 1] = s1;
+    }
+  }
+}
 
 // ------------------------------------------------------- batch (scalars) --
 // One block per system; a finished (frozen) system is skipped.

@@ -109,6 +109,12 @@ class Solver:
         self._check(self.lib.pn_apply(self.ctx, _ptr(x, torch.float32), _ptr(y, torch.float32), int(transpose)))
         return y
 
+    def apply_schur(self, x, y=None):
+        """y_o = -D_o^-1 T_oe x_e and y_e = S x_e (pn_apply_schur); x packed FP32."""
+        y = torch.empty_like(x) if y is None else y
+        self._check(self.lib.pn_apply_schur(self.ctx, _ptr(x, torch.float32), _ptr(y, torch.float32)))
+        return y
+
     def row_weights(self):
         """Diagonal of W in the equilibrated CG variant (pn_row_weights)."""
         w = torch.empty(self.n, dtype=torch.float32, device="cuda")
@@ -126,12 +132,14 @@ class Solver:
                                            _ptr(r, torch.float64) if r is not None else None, C.byref(rel)))
         return rel.value
 
-    KERNELS = {"apply": 0, "apply_t": 1, "apply_eq": 2, "supd": 3, "update": 4}
+    KERNELS = {"apply": 0, "apply_t": 1, "apply_eq": 2, "supd": 3, "update": 4,
+               "odd_w": 5, "even_s": 6, "pcg_xr": 7, "pcg_p": 8}
 
     def bench_kernel(self, kernel, iters=20):
         """Mean milliseconds of one launch of a Krylov-loop kernel in its
         in-loop form (pn_bench_kernel): "apply", "apply_t", "apply_eq",
-        "supd" or "update"."""
+        "supd", "update" (the normal-equation loop) or "odd_w", "even_s",
+        "pcg_xr", "pcg_p" (the even-parity loop)."""
         ms = C.c_double()
         self._check(self.lib.pn_bench_kernel(self.ctx, self.KERNELS[kernel], int(iters), C.byref(ms)))
         return ms.value
@@ -202,6 +210,11 @@ class Solver:
         return x, d
 
     # ---------------------------------------------------------- marshalling --
+    def even_unknowns(self):
+        """Unknowns of the even bands l (the even-parity solve's vectors)."""
+        lay = self.layout
+        return sum(lay.offset[k + 1] - lay.offset[k] for k in range(lay.ncoeff) if int(k ** 0.5 + 1e-9) % 2 == 0)
+
     def rhs_from_q00(self, q00):
         """Right-hand side vector for an isotropic emission Q^{00} per cell
         (coefficient 0 sits at the cell centres; all other entries zero)."""
@@ -219,7 +232,7 @@ def _opts(lib, precision, max_iter, max_refine, inner_tol, use_guess, graph_iter
     opts.inner_tol = float(inner_tol)
     opts.use_guess = int(bool(use_guess))
     opts.graph_iters = int(graph_iters)
-    opts.variant = {"auto": 0, "cgls": 1, "cg": 2, "cg_eq": 3}[variant]
+    opts.variant = {"auto": 0, "cgls": 1, "cg": 2, "cg_eq": 3, "schur": 4}[variant]
     return opts
 
 

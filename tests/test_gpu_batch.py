@@ -82,7 +82,8 @@ def test_batch_mixed_orders_matches_single_and_oracle():
             assert res <= 1.01e-8
             assert abs(res - infos[i]["rel_residual"]) <= 1e-11
             assert err <= 1e-5
-            x1, info1, z1 = single_solve(m, rhs[i], tol=1e-8)
+            # the batch's default inner solver is the equilibrated CG
+            x1, info1, z1 = single_solve(m, rhs[i], tol=1e-8, variant="cg_eq")
             assert z1 == zs[p]
             assert info1["inner_iters"] == infos[i]["inner_iters"]
             assert info1["outer_iters"] == infos[i]["outer_iters"]

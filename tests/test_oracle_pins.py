@@ -4,6 +4,7 @@ from math import pi, sqrt
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import scipy.special
 
 from oracle import sh
@@ -391,3 +392,50 @@ def test_config_p1_direct_residual():
     # symmetric source, symmetric medium: L00 is symmetric in x
     v = lay.view(u, 0)
     np.testing.assert_allclose(v, v[:, :, ::-1], rtol=1e-10)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 5, 7])
+@pytest.mark.parametrize("bc", [0, 1, (0, 1, 0)])
+def test_even_odd_block_structure(order, bc):
+    # The transport couples bands l and l +- 1 only, and a coefficient's band
+    # parity equals the parity of its staggering class, so with the unknowns
+    # split by band parity A = [[D_e, T_eo], [T_oe, D_o]] with D_e, D_o
+    # diagonal and, the transport being skew (vacuum / periodic), T_oe =
+    # -T_eo^T: the even-parity Schur complement S = D_e - T_eo D_o^-1 T_oe
+    # is symmetric positive definite (the GPU's even-parity solver relies on
+    # all of it).
+    from oracle.sh import coeff_lm
+    from oracle.stagger import class_of_k
+    m = config_small(order, (4, 3, 5) if order < 5 else (3, 2, 3), seed=order)
+    A, lay = assemble(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min, bc=bc)
+    for k in range(lay.ncoeff):
+        assert coeff_lm(k)[0] % 2 == sum(class_of_k(k)) % 2
+    par = np.concatenate([np.full(lay.size[k], coeff_lm(k)[0] % 2) for k in range(lay.ncoeff)])
+    E, O = np.nonzero(par == 0)[0], np.nonzero(par == 1)[0]
+    A = A.tocsr()
+    Aee, Aoo = A[E][:, E], A[O][:, O]
+    assert abs(Aee - sp.diags(Aee.diagonal())).max() == 0 and abs(Aoo - sp.diags(Aoo.diagonal())).max() == 0
+    Aeo, Aoe = A[E][:, O], A[O][:, E]
+    assert abs(Aoe + Aeo.T).max() <= 1e-12 * abs(Aeo).max()
+    S = (sp.diags(Aee.diagonal()) - Aeo @ sp.diags(1.0 / Aoo.diagonal()) @ Aoe).toarray()
+    assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+    assert np.linalg.eigvalsh(0.5 * (S + S.T)).min() > 0
+    # and the Schur solve plus back-substitution is the solution of A u = Q
+    b = rhs_isotropic(lay, m.q00[0])
+    de, do = Aee.diagonal(), Aoo.diagonal()
+    ue = np.linalg.solve(S, b[E] - Aeo @ (b[O] / do))
+    u = np.zeros(lay.n)
+    u[E] = ue
+    u[O] = (b[O] - Aoe @ ue) / do
+    assert np.linalg.norm(A @ u - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_neumann_breaks_the_skew_coupling():
+    # under the Neumann boundary the redirected entries make T_oe != -T_eo^T
+    from oracle.sh import coeff_lm
+    m = config_small(3, (4, 3, 5), seed=9)
+    A, lay = assemble(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min, bc=2)
+    par = np.concatenate([np.full(lay.size[k], coeff_lm(k)[0] % 2) for k in range(lay.ncoeff)])
+    E, O = np.nonzero(par == 0)[0], np.nonzero(par == 1)[0]
+    A = A.tocsr()
+    assert abs(A[O][:, E] + A[E][:, O].T).max() > 1.0
