@@ -77,13 +77,13 @@ LOOP_KERNELS = (
      "k_stencil<5,float,ODD_W>: w_o = -D_o^-1 T_oe p_e (odd rows)"),
     ("even_s", lambda n, ne, c: 4 * n + 4 * ne + 8 * c,
      "k_stencil<5,float,EVEN_S>: q_e = D_e p_e + T_eo w_o, <p, q> partials"),
-    ("pcg_xr", lambda n, ne, c: 28 * ne, "k_pcg_vec<1>: x += alpha p, r -= alpha q, <r, M r>, <r, r> partials"),
-    ("pcg_p", lambda n, ne, c: 16 * ne, "k_pcg_vec<2>: p = M r + beta p"),
+    ("pcg_r", lambda n, ne, c: 14 * ne, "k_pcg_vec<1>: r -= alpha q, <r, M r>, <r, r> partials (M in bfloat16)"),
+    ("pcg_xp", lambda n, ne, c: 22 * ne, "k_pcg_vec<2>: x += alpha p, p = M r + beta p (M in bfloat16)"),
     ("apply_eq", lambda n, ne, c: 8 * n + 8 * c, "k_stencil<5,float,APPLY_EQ>: q = W A p (normal-equation loop)"),
     ("supd", lambda n, ne, c: 12 * n + 8 * c, "k_stencil<5,float,SUPD>: s -= alpha A^T q (normal-equation loop)"),
     ("update", lambda n, ne, c: 20 * n, "k_update_xp<float>: x += alpha p, p = s + beta p (normal-equation loop)"),
 )
-SCHUR_LOOP = ("odd_w", "even_s", "pcg_xr", "pcg_p")
+SCHUR_LOOP = ("odd_w", "even_s", "pcg_r", "pcg_xp")
 
 
 def oracle_run(tag):
@@ -295,7 +295,7 @@ def bench_batch(args, quiet=False):
 def profile_kernels(args):
     """Profiling mode for rocprofv3 (--profile-kernels): runs each listed
     kernel of the FP32 Krylov loops of the P5 nebula workload (the plain
-    apply; the even-parity loop odd_w, even_s, pcg_xr, pcg_p; the
+    apply; the even-parity loop odd_w, even_s, pcg_r, pcg_xp; the
     normal-equation loop apply_eq, supd, update) `--profile-iters` times in its in-loop form
     at a fixed z-chunk, then three plain 1 GiB device copies whose counter
     readings calibrate FETCH_SIZE / WRITE_SIZE (bytes per copy known).  Prints
@@ -344,7 +344,7 @@ def main():
     ap.add_argument("--workload", choices=("p5", "batch"), default="p5")
     ap.add_argument("--batch-media", type=int, default=48)
     ap.add_argument("--profile-kernels", default=None, metavar="LIST",
-                    help="profiling mode: comma-separated loop kernels (apply, apply_t, odd_w, even_s, pcg_xr, pcg_p, "
+                    help="profiling mode: comma-separated loop kernels (apply, apply_t, odd_w, even_s, pcg_r, pcg_xp, "
                          "apply_eq, supd, update) "
                          "run in their in-loop form for rocprofv3, then the counter-calibration copies")
     ap.add_argument("--profile-iters", type=int, default=10)

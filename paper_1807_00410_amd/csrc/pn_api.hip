@@ -176,6 +176,7 @@ static void free_all(pn_ctx* c) {
   if (c->gexec_schur) hipGraphExecDestroy(c->gexec_schur);
   hipFree(c->med); hipFree(c->med32);
   for (int i = 0; i < 2; ++i) { hipFree(c->r32[i]); hipFree(c->r64[i]); }
+  hipFree(c->m16);
   hipFree(c->s32); hipFree(c->p32); hipFree(c->q32); hipFree(c->d32); hipFree(c->b32); hipFree(c->x64);
   hipFree(c->s64); hipFree(c->p64); hipFree(c->q64); hipFree(c->d64);
   hipFree(c->st); hipFree(c->partials); hipFree(c->flag);
@@ -442,6 +443,8 @@ pn_status setup_ctx(int order, const pn_grid* grid, const pn_medium* med, void* 
       SETUP_HIP(hipMalloc(v, sizeof(float) * c->nv));
       SETUP_HIP(hipMemsetAsync(*v, 0, sizeof(float) * c->nv, c->stream));  // zero halo invariant
     }
+    SETUP_HIP(hipMalloc(&c->m16, sizeof(uint16_t) * c->nv));
+    SETUP_HIP(hipMemsetAsync(c->m16, 0, sizeof(uint16_t) * c->nv, c->stream));
     SETUP_HIP(hipMalloc(&c->x64, sizeof(double) * c->nv));
     SETUP_HIP(hipMemsetAsync(c->x64, 0, sizeof(double) * c->nv, c->stream));
     SETUP_HIP(hipMalloc(&c->st, sizeof(DevState)));
@@ -673,7 +676,7 @@ extern "C" pn_status pn_bench_apply(pn_ctx* c, int iters, int transpose, double*
 static int pcg_vec_blocks(const pn_ctx* c);
 
 extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* ms) {
-  if (!c || iters < 1 || !ms || kernel < PN_KERNEL_APPLY || kernel > PN_KERNEL_PCG_P)
+  if (!c || iters < 1 || !ms || kernel < PN_KERNEL_APPLY || kernel > PN_KERNEL_PCG_XP)
     return c ? fail(c, PN_ERR_ARG, "bad arguments") : PN_ERR_ARG;
   if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (c->use_lds && kernel != PN_KERNEL_APPLY && kernel != PN_KERNEL_APPLY_T)
@@ -709,15 +712,15 @@ extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* m
       case PN_KERNEL_EVEN_S:
         a.st = c->st; a.partials = c->partials; a.x = c->p32; a.y = c->q32;
         return launch_stencil<float, M_EVEN_S, float>(c, a, c->stream);
-      case PN_KERNEL_PCG_XR:
-      case PN_KERNEL_PCG_P: {
+      case PN_KERNEL_PCG_R:
+      case PN_KERNEL_PCG_XP: {
         const dim3 vg(pcg_vec_blocks(c), c->even.nk);
-        if (k == PN_KERNEL_PCG_XR)
+        if (k == PN_KERNEL_PCG_R)
           hipLaunchKernelGGL(k_pcg_vec<1>, vg, dim3(kBlock), 0, c->stream, c->d32, c->r32[1], c->p32,
-                             (const float*)c->q32, (const float*)c->s32, c->even, c->partials, (const DevState*)c->st);
+                             (const float*)c->q32, (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
         else
           hipLaunchKernelGGL(k_pcg_vec<2>, vg, dim3(kBlock), 0, c->stream, c->d32, c->r32[1], c->p32,
-                             (const float*)c->q32, (const float*)c->s32, c->even, c->partials, (const DevState*)c->st);
+                             (const float*)c->q32, (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
         return hipGetLastError();
       }
       default:
@@ -738,7 +741,7 @@ extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* m
     total = t;
   } else {
     const int seq_cg[3] = {PN_KERNEL_APPLY_EQ, PN_KERNEL_SUPD, PN_KERNEL_UPDATE};
-    const int seq_schur[4] = {PN_KERNEL_ODD_W, PN_KERNEL_EVEN_S, PN_KERNEL_PCG_XR, PN_KERNEL_PCG_P};
+    const int seq_schur[4] = {PN_KERNEL_ODD_W, PN_KERNEL_EVEN_S, PN_KERNEL_PCG_R, PN_KERNEL_PCG_XP};
     const bool sc = kernel >= PN_KERNEL_ODD_W;
     for (int i = 0; i <= iters; ++i) {  // iteration 0 warms up
       for (int j = 0; j < (sc ? 4 : 3); ++j) {
@@ -766,7 +769,7 @@ static pn_status residual(pn_ctx* c, const float* rhs_pad, const double* x_pad, 
   a.x = x_pad; a.x2 = rhs_pad; a.y = r_pad;
   a.partials = c->partials;
   PN_HIP((launch_stencil<double, M_RESID, TO>(c, a, s)));
-  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kBlock), 0, s, c->st, c->partials, c->nblocks);
+  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kFinBlock), 0, s, c->st, c->partials, c->nblocks);
   PN_HIP(hipGetLastError());
   return PN_OK;
 }
@@ -797,11 +800,11 @@ static hipError_t enqueue_iteration(pn_ctx* c, T* d, T* p, T* q, T* s, const T* 
   a.x = p; a.y = q; a.tsign = 1.0;
   hipError_t e = launch_stencil<T, M_APPLY, T>(c, a, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->nblocks);
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, c->nblocks);
   a.x = rin; a.x2 = q; a.y = s; a.y2 = rout; a.tsign = -1.0;
   e = launch_stencil<T, M_TRANSR, T>(c, a, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->nblocks);
+  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, c->nblocks);
   hipLaunchKernelGGL((k_update_xp<T>), dim3(stream_grid(c->nv / (sizeof(T) == 4 ? 4 : 1))), dim3(kBlock), 0, st,
                      d, p, (const T*)s, (long)c->nv, (const DevState*)c->st);
   return hipGetLastError();
@@ -823,11 +826,11 @@ static hipError_t enqueue_iteration_cg(pn_ctx* c, float* d, float* p, float* q, 
                  : eq       ? launch_stencil<float, M_APPLY_EQ, float>(c, a, st)
                             : launch_stencil<float, M_APPLY, float>(c, a, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fin_alpha_cg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, nb);
+  hipLaunchKernelGGL(k_fin_alpha_cg, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, nb);
   a.x = q; a.y = s; a.tsign = -1.0;
   e = c->use_lds ? launch_lds(c, M_SUPD, true, a, st) : launch_stencil<float, M_SUPD, float>(c, a, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fin_beta_cg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, nb);
+  hipLaunchKernelGGL(k_fin_beta_cg, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, nb);
   hipLaunchKernelGGL((k_update_xp<float>), dim3(stream_grid(c->nv / 4)), dim3(kBlock), 0, st, d, p,
                      (const float*)s, (long)c->nv, (const DevState*)c->st);
   return hipGetLastError();
@@ -855,13 +858,13 @@ static hipError_t enqueue_iteration_schur(pn_ctx* c, hipStream_t st) {
   a.x = c->p32; a.y = c->q32;
   e = launch_stencil<float, M_EVEN_S, float>(c, a, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fin_alpha_pcg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, c->nblocks);
+  hipLaunchKernelGGL(k_fin_alpha_pcg, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, c->nblocks);
   const dim3 vg(pcg_vec_blocks(c), c->even.nk);
   hipLaunchKernelGGL(k_pcg_vec<1>, vg, dim3(kBlock), 0, st, c->d32, c->r32[1], c->p32, (const float*)c->q32,
-                     (const float*)c->s32, c->even, c->partials, (const DevState*)c->st);
-  hipLaunchKernelGGL(k_fin_beta_pcg, dim3(1), dim3(kBlock), 0, st, c->st, c->partials, (int)(vg.x * vg.y));
+                     (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
+  hipLaunchKernelGGL(k_fin_beta_pcg, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, (int)(vg.x * vg.y));
   hipLaunchKernelGGL(k_pcg_vec<2>, vg, dim3(kBlock), 0, st, c->d32, c->r32[1], c->p32, (const float*)c->q32,
-                     (const float*)c->s32, c->even, c->partials, (const DevState*)c->st);
+                     (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
   return hipGetLastError();
 }
 
@@ -1007,14 +1010,14 @@ static pn_status net_scale(pn_ctx* c, const float* rhs_pad, hipStream_t s, doubl
   StencilArgs a = base_args(c);
   a.x = c->u64; a.y = c->w64; a.partials = c->partials;
   PN_HIP((launch_stencil<double, M_APPLY, double>(c, a, s)));
-  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kBlock), 0, s, c->st_net, c->partials, c->nblocks);
+  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kFinBlock), 0, s, c->st_net, c->partials, c->nblocks);
   PN_HIP(hipMemcpyAsync(c->st_host, c->st_net, sizeof(DevState), hipMemcpyDeviceToHost, s));
   PN_HIP(hipStreamSynchronize(s));
   const double au2 = c->st_host->rtrue2;
   a = base_args(c);
   a.x = c->u64; a.x2 = rhs_pad; a.y = c->r32[1]; a.partials = c->partials;
   PN_HIP((launch_stencil<double, M_RESID, float>(c, a, s)));
-  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kBlock), 0, s, c->st_net, c->partials, c->nblocks);
+  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kFinBlock), 0, s, c->st_net, c->partials, c->nblocks);
   PN_HIP(hipMemcpyAsync(c->st_host, c->st_net, sizeof(DevState), hipMemcpyDeviceToHost, s));
   PN_HIP(hipStreamSynchronize(s));
   const double rr = c->st_host->rtrue2, bb = c->st_host->bb2;
@@ -1132,6 +1135,9 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     PN_HIP((launch_stencil<float, M_ODD_BACK, float>(c, a, c->sstream)));
     a.x = c->q32; a.y = c->s32;
     PN_HIP((launch_stencil<float, M_EVEN_JAC, float>(c, a, c->sstream)));
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(c->nv)), dim3(kBlock), 0, c->sstream, (const float*)c->s32, c->m16,
+                       (long)c->nv);
+    PN_HIP(hipGetLastError());
   }
   hipStream_t ss = c->sstream;
   DevState init;
@@ -1228,9 +1234,9 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
         PN_HIP((launch_stencil<float, M_ODD_BACK, float>(c, b, ss)));
         b.x = q; b.x2 = r0; b.y = r1;
         PN_HIP((launch_stencil<float, M_EVEN_RHS, float>(c, b, ss)));
-        hipLaunchKernelGGL(k_pcg_vec<0>, vg, dim3(kBlock), 0, ss, d, r1, p, (const float*)q, (const float*)s,
+        hipLaunchKernelGGL(k_pcg_vec<0>, vg, dim3(kBlock), 0, ss, d, r1, p, (const float*)q, (const uint16_t*)c->m16,
                            c->even, c->partials, (const DevState*)c->st);
-        hipLaunchKernelGGL(k_fin_init_pcg, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials, (int)(vg.x * vg.y),
+        hipLaunchKernelGGL(k_fin_init_pcg, dim3(1), dim3(kFinBlock), 0, ss, c->st, c->partials, (int)(vg.x * vg.y),
                            itol * itol);
         PN_HIP(hipGetLastError());
         for (;;) {
@@ -1253,7 +1259,7 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
       if (eq) {  // r1 = W r0; the inner solve tracks <r, W r>
         a.x = r0; a.y = r1;
         PN_HIP((launch_stencil<float, M_EQS, float>(c, a, ss)));
-        hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials, c->nblocks);
+        hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(kFinBlock), 0, ss, c->st, c->partials, c->nblocks);
         PN_HIP(hipGetLastError());
         rs = r1;
       }
@@ -1261,7 +1267,7 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     a.x = rs; a.y = s; a.tsign = -1.0;
     if (cg && c->use_lds) PN_HIP(launch_lds(c, M_APPLY, true, a, ss));
     else PN_HIP((launch_stencil<T, M_APPLY, T>(c, a, ss)));
-    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, ss, c->st, c->partials,
+    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, ss, c->st, c->partials,
                        (cg && c->use_lds) ? c->lnblocks : c->nblocks, itol * itol);
     PN_HIP(hipGetLastError());
     PN_HIP(hipMemcpyAsync(p, s, sizeof(T) * c->nv, hipMemcpyDeviceToDevice, ss));  // p = s

@@ -147,7 +147,7 @@ hipError_t vec_all(const pn_batch* b, hipStream_t s) {
 
 template <int WHICH>
 hipError_t fin_all(const pn_batch* b, hipStream_t s) {
-  hipLaunchKernelGGL((k_fin_batch<WHICH>), dim3(b->nsys), dim3(kBlock), 0, s, (const SysArgs*)b->sys);
+  hipLaunchKernelGGL((k_fin_batch<WHICH>), dim3(b->nsys), dim3(kFinBlock), 0, s, (const SysArgs*)b->sys);
   return hipGetLastError();
 }
 

@@ -67,6 +67,7 @@ struct pn_ctx {
   float* r32[2] = {nullptr, nullptr};
   float *s32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr, *b32 = nullptr;
   double* x64 = nullptr;    // FP64 iterate (padded)
+  uint16_t* m16 = nullptr;  // even-parity PCG preconditioner, bfloat16 (padded)
   // FP64 Krylov workspace, allocated on first use
   double* r64[2] = {nullptr, nullptr};
   double *s64 = nullptr, *p64 = nullptr, *q64 = nullptr, *d64 = nullptr;
@@ -141,8 +142,9 @@ inline SolveBytes solve_bytes(const pn_ctx* c, bool fp64, bool cg, bool eq) {
 }
 
 // Even-parity PCG: per iteration the odd rows (read the even vector, write the
-// odd one), the even rows (read both, write the even one), x/r (5 even reads,
-// 2 writes), p (3 reads, 1 write); the medium per stencil pass.
+// odd one), the even rows (read both, write the even one), r (r, q, m in
+// bfloat16; write r), x/p (x, p, r, m; write x, p); the medium per stencil
+// pass.
 inline SolveBytes schur_bytes(const pn_ctx* c) {
   double ne = 0.0;
   for (int j = 0; j < c->even.nk; ++j) {
@@ -151,7 +153,7 @@ inline SolveBytes schur_bytes(const pn_ctx* c) {
   }
   const double n = (double)c->n, no = n - ne, cells = (double)c->nx * c->ny * c->nz;
   SolveBytes b;
-  b.per_iter = (ne + no) * 4.0 + (n + ne) * 4.0 + 7.0 * ne * 4.0 + 4.0 * ne * 4.0 + 16.0 * cells;
+  b.per_iter = (ne + no) * 4.0 + (n + ne) * 4.0 + 3.5 * ne * 4.0 + 5.5 * ne * 4.0 + 16.0 * cells;
   b.per_start = 3.0 * n * 4.0 + 4.0 * ne * 4.0 + 16.0 * cells + (ne + n) * 4.0 + 12.0 * n;
   b.per_resid = 16.0 * n + 8.0 * cells;
   return b;

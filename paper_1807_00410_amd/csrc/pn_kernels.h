@@ -544,23 +544,30 @@ __global__ void __launch_bounds__(kBlock, PN_STENCIL_WPE) k_stencil_batch(const 
 }
 
 // ------------------------------------------------------------- finalize --
-// Sum of partials[2*i + j] over i < n in a fixed order (one block).
+// Sum of partials[2*i + j] over i < n in a fixed order by one block of
+// kFinBlock threads; the sums are valid in thread 0 (the only reader).
+constexpr int kFinBlock = 1024;
 __device__ __forceinline__ void grid_sum2(const double* __restrict__ p, int n, double& s0, double& s1) {
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) { a += p[2 * i]; b += p[2 * i + 1]; }
-  __shared__ double red[2][kBlock];
-  red[0][threadIdx.x] = a;
-  red[1][threadIdx.x] = b;
-  __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] += red[1][threadIdx.x + w];
-    }
-    __syncthreads();
+  const double2* __restrict__ p2 = reinterpret_cast<const double2*>(p);
+#pragma unroll 4
+  for (int i = threadIdx.x; i < n; i += kFinBlock) {
+    const double2 v = p2[i];
+    a += v.x;
+    b += v.y;
   }
-  s0 = red[0][0];
-  s1 = red[1][0];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __shared__ double red[2][kFinBlock / 64];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][w] = a; red[1][w] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = 0.0; b = 0.0;
+    for (int i = 0; i < kFinBlock / 64; ++i) { a += red[0][i]; b += red[1][i]; }
+  }
+  s0 = a;
+  s1 = b;
 }
 
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
@@ -681,13 +688,13 @@ __device__ __forceinline__ void fin_resid(DevState* st, const double* partials, 
   }
 }
 
-static __global__ void __launch_bounds__(kBlock) k_fin_alpha(DevState* st, const double* partials, int n) { fin_alpha(st, partials, n); }
-static __global__ void __launch_bounds__(kBlock) k_fin_beta(DevState* st, const double* partials, int n) { fin_beta(st, partials, n); }
-static __global__ void __launch_bounds__(kBlock) k_fin_init(DevState* st, const double* partials, int n, double inner_tol2) { fin_init(st, partials, n, inner_tol2); }
-static __global__ void __launch_bounds__(kBlock) k_fin_alpha_cg(DevState* st, const double* partials, int n) { fin_alpha_cg(st, partials, n); }
-static __global__ void __launch_bounds__(kBlock) k_fin_beta_cg(DevState* st, const double* partials, int n) { fin_beta_cg(st, partials, n); }
-static __global__ void __launch_bounds__(kBlock) k_fin_resid(DevState* st, const double* partials, int n) { fin_resid(st, partials, n); }
-static __global__ void __launch_bounds__(kBlock) k_fin_rr(DevState* st, const double* partials, int n) { fin_rr(st, partials, n); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_alpha(DevState* st, const double* partials, int n) { fin_alpha(st, partials, n); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_beta(DevState* st, const double* partials, int n) { fin_beta(st, partials, n); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_init(DevState* st, const double* partials, int n, double inner_tol2) { fin_init(st, partials, n, inner_tol2); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_alpha_cg(DevState* st, const double* partials, int n) { fin_alpha_cg(st, partials, n); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_beta_cg(DevState* st, const double* partials, int n) { fin_beta_cg(st, partials, n); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_resid(DevState* st, const double* partials, int n) { fin_resid(st, partials, n); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_rr(DevState* st, const double* partials, int n) { fin_rr(st, partials, n); }
 
 // ---------------------------------------------------------------- vector --
 // Non-temporal float4 access for the pure streaming update: the stream is
@@ -880,9 +887,19 @@ __device__ __forceinline__ void fin_init_pcg(DevState* st, const double* partial
   }
 }
 
-static __global__ void __launch_bounds__(kBlock) k_fin_alpha_pcg(DevState* st, const double* partials, int n) { fin_alpha_pcg(st, partials, n); }
-static __global__ void __launch_bounds__(kBlock) k_fin_beta_pcg(DevState* st, const double* partials, int n) { fin_beta_pcg(st, partials, n); }
-static __global__ void __launch_bounds__(kBlock) k_fin_init_pcg(DevState* st, const double* partials, int n, double inner_tol2) { fin_init_pcg(st, partials, n, inner_tol2); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_alpha_pcg(DevState* st, const double* partials, int n) { fin_alpha_pcg(st, partials, n); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_beta_pcg(DevState* st, const double* partials, int n) { fin_beta_pcg(st, partials, n); }
+static __global__ void __launch_bounds__(kFinBlock) k_fin_init_pcg(DevState* st, const double* partials, int n, double inner_tol2) { fin_init_pcg(st, partials, n, inner_tol2); }
+
+// bfloat16 copy (round to nearest even) of a float vector
+static __global__ void __launch_bounds__(kBlock) k_to_bf16(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                                           long n) {
+  const long stride = (long)gridDim.x * kBlock;
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const uint32_t u = __float_as_uint(src[i]);
+    dst[i] = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+}
 
 // The even-band coefficient arrays of a padded vector: array j of the list
 // starts at k[j] * cs; each is cs floats (a multiple of 64).  Grid: (blocks
@@ -894,42 +911,52 @@ struct EvenSlots {
   long long cs;
 };
 
-// OP 0 (init):    p = m r                        [<r, m r>, <r, r>]
-// OP 1 (x, r):    x += alpha p, r -= alpha q     [<r, m r>, <r, r>]
-// OP 2 (p):       p = m r + beta p
+// The preconditioner m is stored in bfloat16 (it only has to be the same
+// positive diagonal in every use; 8 bits of mantissa keep it within 0.4% of
+// 1 / diag(S)), which halves its share of the vector traffic.
+__device__ __forceinline__ float4 ld_bf4(const uint2* p) {
+  const uint2 v = *p;
+  return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u), __uint_as_float(v.y << 16),
+                     __uint_as_float(v.y & 0xffff0000u));
+}
+
+// OP 0 (init):    p = m r                              [<r, m r>, <r, r>]
+// OP 1 (r):       r -= alpha q                         [<r, m r>, <r, r>]
+// OP 2 (x, p):    x += alpha p, p = m r + beta p
+// (x is advanced together with p, one pass later than r: alpha is still the
+// step of this iteration there, and that pass runs after the stop test too)
 template <int OP>
 __global__ void __launch_bounds__(kBlock) k_pcg_vec(float* __restrict__ x, float* __restrict__ r,
                                                     float* __restrict__ p, const float* __restrict__ q,
-                                                    const float* __restrict__ m, const EvenSlots es,
+                                                    const uint16_t* __restrict__ m, const EvenSlots es,
                                                     double* __restrict__ partials, const DevState* st) {
   if (OP != 0 && st->done) return;
   const long long base = (long long)es.k[blockIdx.y] * es.cs;
   const long long n4 = es.cs >> 2;
   const long long stride = (long long)gridDim.x * kBlock;
-  const float al = OP == 1 ? float(st->alpha) : 0.f, be = OP == 2 ? float(st->beta) : 0.f;
+  const float al = OP != 0 ? float(st->alpha) : 0.f, be = OP == 2 ? float(st->beta) : 0.f;
   float4* x4 = reinterpret_cast<float4*>(x + base);
   float4* r4 = reinterpret_cast<float4*>(r + base);
   float4* p4 = reinterpret_cast<float4*>(p + base);
   const float4* q4 = reinterpret_cast<const float4*>(q + base);
-  const float4* m4 = reinterpret_cast<const float4*>(m + base);
+  const uint2* m4 = reinterpret_cast<const uint2*>(m + base);
   double s0 = 0.0, s1 = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride) {
     float4 rv = ld_nt(r4 + i);
-    const float4 mv = ld_nt(m4 + i);
+    const float4 mv = ld_bf4(m4 + i);
     if constexpr (OP == 1) {
-      const float4 pv = ld_nt(p4 + i), qv = ld_nt(q4 + i);
-      float4 xv = ld_nt(x4 + i);
-      xv.x = __fmaf_rn(al, pv.x, xv.x); xv.y = __fmaf_rn(al, pv.y, xv.y);
-      xv.z = __fmaf_rn(al, pv.z, xv.z); xv.w = __fmaf_rn(al, pv.w, xv.w);
+      const float4 qv = ld_nt(q4 + i);
       rv.x = __fmaf_rn(-al, qv.x, rv.x); rv.y = __fmaf_rn(-al, qv.y, rv.y);
       rv.z = __fmaf_rn(-al, qv.z, rv.z); rv.w = __fmaf_rn(-al, qv.w, rv.w);
-      st_nt(x4 + i, xv);
       st_nt(r4 + i, rv);
     }
     if constexpr (OP == 2) {
-      float4 pv = ld_nt(p4 + i);
+      float4 pv = ld_nt(p4 + i), xv = ld_nt(x4 + i);
+      xv.x = __fmaf_rn(al, pv.x, xv.x); xv.y = __fmaf_rn(al, pv.y, xv.y);
+      xv.z = __fmaf_rn(al, pv.z, xv.z); xv.w = __fmaf_rn(al, pv.w, xv.w);
       pv.x = __fmaf_rn(be, pv.x, mv.x * rv.x); pv.y = __fmaf_rn(be, pv.y, mv.y * rv.y);
       pv.z = __fmaf_rn(be, pv.z, mv.z * rv.z); pv.w = __fmaf_rn(be, pv.w, mv.w * rv.w);
+      st_nt(x4 + i, xv);
       st_nt(p4 + i, pv);
     } else {
       const float4 z = make_float4(mv.x * rv.x, mv.y * rv.y, mv.z * rv.z, mv.w * rv.w);
@@ -953,7 +980,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_vec(float* __restrict__ x, float
 enum BatchFin { BF_ALPHA = 0, BF_BETA = 1, BF_INIT = 2, BF_RESID = 3, BF_ALPHA_CG = 4, BF_BETA_CG = 5, BF_RR = 6 };
 
 template <int WHICH>
-__global__ void __launch_bounds__(kBlock) k_fin_batch(const SysArgs* __restrict__ sys) {
+__global__ void __launch_bounds__(kFinBlock) k_fin_batch(const SysArgs* __restrict__ sys) {
   const SysArgs* s = sys + blockIdx.x;
   DevState* st = s->a.st;
   if (st->frozen) return;
