@@ -14,8 +14,8 @@ Also reported (JSON keys):
                 launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
                 summary when it was taken on the current kernel sources.
   loop_kernels  the same figures for every kernel of the loop (the plain
-                apply; w_o = -D_o^-1 T_oe p_e, q_e = S p_e and the two PCG
-                vector passes; and the kernels of the normal-equation loop,
+                apply; w_o = -D_o^-1 T_oe p_e, r_e -= alpha S p_e and the PCG
+                x/p pass; and the kernels of the normal-equation loop,
                 q = W A p, s -= alpha A^T q, the x/p update).
   cg_eq_normal_equations  the previous default inner solver (CG on the
                 row-equilibrated normal equations) on the same system.
@@ -74,16 +74,15 @@ def load_traffic(kernel_hash, kernel):
 LOOP_KERNELS = (
     ("apply", lambda n, ne, c: 8 * n + 8 * c, "k_stencil<5,float,APPLY>: y = A x"),
     ("odd_w", lambda n, ne, c: 4 * ne + 4 * (n - ne) + 8 * c,
-     "k_stencil<5,float,ODD_W>: w_o = -D_o^-1 T_oe p_e (odd rows)"),
-    ("even_s", lambda n, ne, c: 4 * n + 4 * ne + 8 * c,
-     "k_stencil<5,float,EVEN_S>: q_e = D_e p_e + T_eo w_o, <p, q> partials"),
-    ("pcg_r", lambda n, ne, c: 14 * ne, "k_pcg_vec<1>: r -= alpha q, <r, M r>, <r, r> partials (M in bfloat16)"),
+     "k_stencil<5,float,ODD_W>: w_o = -D_o^-1 T_oe p_e (odd rows), <p, S p> partials"),
+    ("even_r", lambda n, ne, c: 4 * n + 4 * ne + 2 * ne + 4 * ne + 8 * c,
+     "k_stencil<5,float,EVEN_SR>: r_e -= alpha (D_e p_e + T_eo w_o) (even rows), <r, M r>, <r, r> partials"),
     ("pcg_xp", lambda n, ne, c: 22 * ne, "k_pcg_vec<2>: x += alpha p, p = M r + beta p (M in bfloat16)"),
     ("apply_eq", lambda n, ne, c: 8 * n + 8 * c, "k_stencil<5,float,APPLY_EQ>: q = W A p (normal-equation loop)"),
     ("supd", lambda n, ne, c: 12 * n + 8 * c, "k_stencil<5,float,SUPD>: s -= alpha A^T q (normal-equation loop)"),
     ("update", lambda n, ne, c: 20 * n, "k_update_xp<float>: x += alpha p, p = s + beta p (normal-equation loop)"),
 )
-SCHUR_LOOP = ("odd_w", "even_s", "pcg_r", "pcg_xp")
+SCHUR_LOOP = ("odd_w", "even_r", "pcg_xp")
 
 
 def oracle_run(tag):
@@ -295,7 +294,7 @@ def bench_batch(args, quiet=False):
 def profile_kernels(args):
     """Profiling mode for rocprofv3 (--profile-kernels): runs each listed
     kernel of the FP32 Krylov loops of the P5 nebula workload (the plain
-    apply; the even-parity loop odd_w, even_s, pcg_r, pcg_xp; the
+    apply; the even-parity loop odd_w, even_r, pcg_xp; the
     normal-equation loop apply_eq, supd, update) `--profile-iters` times in its in-loop form
     at a fixed z-chunk, then three plain 1 GiB device copies whose counter
     readings calibrate FETCH_SIZE / WRITE_SIZE (bytes per copy known).  Prints
@@ -323,6 +322,42 @@ def profile_kernels(args):
     s.close()
 
 
+def accuracy_check(args):
+    """--accuracy: the P5 128^3 nebula (g = 0 and 0.5) solved to 1e-8 by the
+    default inner solver, the equilibrated normal equations and FP64 CGLS,
+    each compared with the oracle's FP64 solution to 1e-12
+    (refdata/ref_p5_128_g<g>.npy, written by tests/golden/make_references.py;
+    workloads without that file are skipped).  Prints one JSON line."""
+    import numpy as np
+    import torch
+    from synth import config_p5_nebula
+    from paper_1807_00410_amd.solver import Solver
+    out = {}
+    for g in (0.0, 0.5):
+        path = os.path.join(ROOT, "refdata", "ref_p5_128_g%g.npy" % g)
+        if not os.path.exists(path):
+            continue
+        ref = np.load(path).astype(np.float64)
+        m = config_p5_nebula(n=128, seed=3, g=g)
+        s = Solver(m.order, m.dims, torch.as_tensor(m.sigma_t).cuda(), torch.as_tensor(m.albedo).cuda(), g=m.g,
+                   sigma_t_min=m.sigma_t_min)
+        rhs = s.rhs_from_q00(torch.as_tensor(m.q00[0]).cuda())
+        res = {}
+        for name, kw in (("even-parity PCG (default)", {}), ("CG, equilibrated normal equations", {"variant": "cg_eq"}),
+                         ("CGLS in FP64", {"precision": "fp64"})):
+            x, info = s.solve(rhs, tol=args.tol, **kw)
+            xs = x.cpu().numpy()
+            res[name] = {"iters": info["inner_iters"], "rel_residual": info["rel_residual"], "seconds": info["seconds"],
+                         "rel_l2_vs_oracle": float(np.linalg.norm(xs - ref) / np.linalg.norm(ref)),
+                         "max_abs_err_over_max": float(np.max(np.abs(xs - ref)) / np.max(np.abs(ref)))}
+            print("[bench] g=%g %-34s iters %5d rel %.3g rel-L2 vs oracle %.3e" % (
+                g, name, info["inner_iters"], info["rel_residual"], res[name]["rel_l2_vs_oracle"]), file=sys.stderr,
+                flush=True)
+        out["p5_128_g%g" % g] = res
+        s.close()
+    print(json.dumps({"accuracy_vs_oracle": out, "tol": args.tol}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,10 +379,12 @@ def main():
     ap.add_argument("--workload", choices=("p5", "batch"), default="p5")
     ap.add_argument("--batch-media", type=int, default=48)
     ap.add_argument("--profile-kernels", default=None, metavar="LIST",
-                    help="profiling mode: comma-separated loop kernels (apply, apply_t, odd_w, even_s, pcg_r, pcg_xp, "
+                    help="profiling mode: comma-separated loop kernels (apply, apply_t, odd_w, even_r, pcg_xp, "
                          "apply_eq, supd, update) "
                          "run in their in-loop form for rocprofv3, then the counter-calibration copies")
     ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--accuracy", action="store_true",
+                    help="compare the P5 128^3 solutions with the oracle's reference solutions in refdata/")
     ap.add_argument("--profile-zchunk", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -356,6 +393,9 @@ def main():
         sys.exit(2)
     if args.profile_kernels:
         profile_kernels(args)
+        return
+    if args.accuracy:
+        accuracy_check(args)
         return
     if args.workload == "batch":
         bench_batch(args)

@@ -289,14 +289,14 @@ pn_status pn_bench_apply(pn_ctx* ctx, int iters, int transpose, double* ms_per_a
 #define PN_KERNEL_UPDATE 4
 /* The kernels of the even-parity loop (PN_VARIANT_SCHUR), timed inside its
  * own kernel sequence:
- *   PN_KERNEL_ODD_W      w_o = -D_o^-1 T_oe p_e (odd rows)
- *   PN_KERNEL_EVEN_S     q_e = D_e p_e + T_eo w_o with the FP64 partials of <p, q>
- *   PN_KERNEL_PCG_R      r -= alpha q with <r, M r>, <r, r>
+ *   PN_KERNEL_ODD_W      w_o = -D_o^-1 T_oe p_e (odd rows) with the FP64
+ *                        partials of <p, S p> = <p_e, D_e p_e> + <w_o, D_o w_o>
+ *   PN_KERNEL_EVEN_R     r_e -= alpha (D_e p_e + T_eo w_o) (even rows) with
+ *                        <r, M r>, <r, r>
  *   PN_KERNEL_PCG_XP     x += alpha p, p = M r + beta p */
 #define PN_KERNEL_ODD_W 5
-#define PN_KERNEL_EVEN_S 6
-#define PN_KERNEL_PCG_R 7
-#define PN_KERNEL_PCG_XP 8
+#define PN_KERNEL_EVEN_R 6
+#define PN_KERNEL_PCG_XP 7
 pn_status pn_bench_kernel(pn_ctx* ctx, int kernel, int iters, double* ms);
 
 /* Launch tuning: planes of z handled per thread block in the stencil apply

@@ -591,9 +591,10 @@ extern "C" pn_status pn_apply_schur(pn_ctx* c, const float* x, float* y) {
   if (!schur_ok(c)) return fail(c, PN_ERR_ARG, "the even-parity operator needs T_oe = -T_eo^T (no Neumann axis) and positive extinction in every cell");
   PN_HIP((launch_pack<float, float, 0>(c, x, c->p32, c->stream)));
   StencilArgs a = base_args(c);
+  a.partials = c->partials;
   a.x = c->p32; a.y = c->p32;  // odd slots of p32 <- -D_o^-1 T_oe x_e
   PN_HIP((launch_stencil<float, M_ODD_W, float>(c, a, c->stream)));
-  a.partials = c->partials; a.x = c->p32; a.y = c->q32;
+  a.x = c->p32; a.y = c->q32;
   PN_HIP((launch_stencil<float, M_EVEN_S, float>(c, a, c->stream)));
   // y: even bands from q32, odd bands from p32
   PN_HIP((launch_pack<float, float, 1>(c, c->q32, y, c->stream)));
@@ -707,20 +708,15 @@ extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* m
         a.x = c->q32; a.y = c->s32;
         return launch_stencil<float, M_SUPD, float>(c, a, c->stream);
       case PN_KERNEL_ODD_W:
-        a.st = c->st; a.x = c->p32; a.y = c->p32;
+        a.st = c->st; a.partials = c->partials; a.x = c->p32; a.y = c->p32;
         return launch_stencil<float, M_ODD_W, float>(c, a, c->stream);
-      case PN_KERNEL_EVEN_S:
-        a.st = c->st; a.partials = c->partials; a.x = c->p32; a.y = c->q32;
-        return launch_stencil<float, M_EVEN_S, float>(c, a, c->stream);
-      case PN_KERNEL_PCG_R:
+      case PN_KERNEL_EVEN_R:
+        a.st = c->st; a.partials = c->partials; a.x = c->p32; a.y = c->r32[1]; a.m16 = c->m16;
+        return launch_stencil<float, M_EVEN_SR, float>(c, a, c->stream);
       case PN_KERNEL_PCG_XP: {
         const dim3 vg(pcg_vec_blocks(c), c->even.nk);
-        if (k == PN_KERNEL_PCG_R)
-          hipLaunchKernelGGL(k_pcg_vec<1>, vg, dim3(kBlock), 0, c->stream, c->d32, c->r32[1], c->p32,
-                             (const float*)c->q32, (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
-        else
-          hipLaunchKernelGGL(k_pcg_vec<2>, vg, dim3(kBlock), 0, c->stream, c->d32, c->r32[1], c->p32,
-                             (const float*)c->q32, (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
+        hipLaunchKernelGGL(k_pcg_vec<2>, vg, dim3(kBlock), 0, c->stream, c->d32, c->r32[1], c->p32,
+                           (const float*)c->q32, (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
         return hipGetLastError();
       }
       default:
@@ -741,10 +737,10 @@ extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* m
     total = t;
   } else {
     const int seq_cg[3] = {PN_KERNEL_APPLY_EQ, PN_KERNEL_SUPD, PN_KERNEL_UPDATE};
-    const int seq_schur[4] = {PN_KERNEL_ODD_W, PN_KERNEL_EVEN_S, PN_KERNEL_PCG_R, PN_KERNEL_PCG_XP};
+    const int seq_schur[3] = {PN_KERNEL_ODD_W, PN_KERNEL_EVEN_R, PN_KERNEL_PCG_XP};
     const bool sc = kernel >= PN_KERNEL_ODD_W;
     for (int i = 0; i <= iters; ++i) {  // iteration 0 warms up
-      for (int j = 0; j < (sc ? 4 : 3); ++j) {
+      for (int j = 0; j < 3; ++j) {
         const int k = sc ? seq_schur[j] : seq_cg[j];
         if (k == kernel) PN_HIP(hipEventRecord(e0, c->stream));
         PN_HIP(launch(k));
@@ -851,18 +847,18 @@ static hipError_t enqueue_iteration_schur(pn_ctx* c, hipStream_t st) {
   StencilArgs a = base_args(c);
   a.st = c->st;
   a.tsign = 1.0;
+  a.partials = c->partials;
+  // w_o = -D_o^-1 T_oe p_e with the partials of <p, S p> = <p_e, D_e p_e> + <w_o, D_o w_o>
   a.x = c->p32; a.y = c->p32;
   hipError_t e = launch_stencil<float, M_ODD_W, float>(c, a, st);
   if (e != hipSuccess) return e;
-  a.partials = c->partials;
-  a.x = c->p32; a.y = c->q32;
-  e = launch_stencil<float, M_EVEN_S, float>(c, a, st);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fin_alpha_pcg, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, c->nblocks);
+  // r -= alpha (D_e p_e + T_eo w_o) with the partials of <r, M r>, <r, r>
+  a.x = c->p32; a.y = c->r32[1]; a.m16 = c->m16;
+  e = launch_stencil<float, M_EVEN_SR, float>(c, a, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fin_beta_pcg, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, c->nblocks);
   const dim3 vg(pcg_vec_blocks(c), c->even.nk);
-  hipLaunchKernelGGL(k_pcg_vec<1>, vg, dim3(kBlock), 0, st, c->d32, c->r32[1], c->p32, (const float*)c->q32,
-                     (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
-  hipLaunchKernelGGL(k_fin_beta_pcg, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, (int)(vg.x * vg.y));
   hipLaunchKernelGGL(k_pcg_vec<2>, vg, dim3(kBlock), 0, st, c->d32, c->r32[1], c->p32, (const float*)c->q32,
                      (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
   return hipGetLastError();

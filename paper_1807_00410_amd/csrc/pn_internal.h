@@ -141,10 +141,9 @@ inline SolveBytes solve_bytes(const pn_ctx* c, bool fp64, bool cg, bool eq) {
   return b;
 }
 
-// Even-parity PCG: per iteration the odd rows (read the even vector, write the
-// odd one), the even rows (read both, write the even one), r (r, q, m in
-// bfloat16; write r), x/p (x, p, r, m; write x, p); the medium per stencil
-// pass.
+// Even-parity PCG: per iteration the odd rows (read the even part of p,
+// write the odd part), the even rows (read all of p, r and m in bfloat16,
+// write r), x/p (x, p, r, m; write x, p); the medium per stencil pass.
 inline SolveBytes schur_bytes(const pn_ctx* c) {
   double ne = 0.0;
   for (int j = 0; j < c->even.nk; ++j) {
@@ -153,7 +152,7 @@ inline SolveBytes schur_bytes(const pn_ctx* c) {
   }
   const double n = (double)c->n, no = n - ne, cells = (double)c->nx * c->ny * c->nz;
   SolveBytes b;
-  b.per_iter = (ne + no) * 4.0 + (n + ne) * 4.0 + 3.5 * ne * 4.0 + 5.5 * ne * 4.0 + 16.0 * cells;
+  b.per_iter = 4.0 * (ne + no) + (4.0 * n + 10.0 * ne) + 22.0 * ne + 16.0 * cells;
   b.per_start = 3.0 * n * 4.0 + 4.0 * ne * 4.0 + 16.0 * cells + (ne + n) * 4.0 + 12.0 * n;
   b.per_resid = 16.0 * n + 8.0 * cells;
   return b;
@@ -219,7 +218,8 @@ inline hipError_t launch_stencil(const pn_ctx* c, const StencilArgs& a, hipStrea
          : (MODE == M_EVEN_S) ? K_F32_EVEN_S
          : (MODE == M_EVEN_RHS) ? K_F32_EVEN_RHS
          : (MODE == M_ODD_BACK) ? K_F32_ODD_BACK
-         : (MODE == M_EVEN_JAC) ? K_F32_EVEN_JAC : K_F32_TRANSR;
+         : (MODE == M_EVEN_JAC) ? K_F32_EVEN_JAC
+         : (MODE == M_EVEN_SR) ? K_F32_EVEN_SR : K_F32_TRANSR;
   else if constexpr (MODE == M_APPLY) kind = K_F64_APPLY;
   else if constexpr (MODE == M_TRANSR) kind = K_F64_TRANSR;
   else kind = (sizeof(TO) == 4) ? K_F64_RESID32 : K_F64_RESID64;

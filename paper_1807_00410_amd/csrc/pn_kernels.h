@@ -63,7 +63,7 @@ struct DevState {
 enum Mode {
   M_APPLY = 0, M_TRANSR = 1, M_RESID = 2, M_SUPD = 3, M_APPLY_EQ = 4, M_EQS = 5,
   // even-parity (Schur complement) solve, rows of one band parity only
-  M_ODD_W = 6, M_EVEN_S = 7, M_EVEN_RHS = 8, M_ODD_BACK = 9, M_EVEN_JAC = 10
+  M_ODD_W = 6, M_EVEN_S = 7, M_EVEN_RHS = 8, M_ODD_BACK = 9, M_EVEN_JAC = 10, M_EVEN_SR = 11
 };
 
 // Band parity of the rows a mode computes: 0 all, 1 even l, 2 odd l.  The
@@ -73,7 +73,8 @@ enum Mode {
 // [[D_e, T_eo], [T_oe, D_o]] with D_e, D_o diagonal (and T_oe = -T_eo^T when
 // no axis is Neumann).
 constexpr int mode_rows(int m) {
-  return (m == M_EVEN_S || m == M_EVEN_RHS || m == M_EVEN_JAC) ? 1 : (m == M_ODD_W || m == M_ODD_BACK) ? 2 : 0;
+  return (m == M_EVEN_S || m == M_EVEN_RHS || m == M_EVEN_JAC || m == M_EVEN_SR) ? 1
+         : (m == M_ODD_W || m == M_ODD_BACK) ? 2 : 0;
 }
 constexpr int class_parity(int c) { return ((c & 1) + ((c >> 1) & 1) + ((c >> 2) & 1)) & 1; }
 
@@ -111,6 +112,7 @@ struct StencilArgs {
   double omg[8];       // 1 - g^l, l = 0..7
   const float2* med32; // padded cells (sigma_a, sigma_s) in FP32
   const float2* med;   // padded cells (sigma_t, albedo) as given (FP64 kernels)
+  const uint16_t* m16; // M_EVEN_SR: bfloat16 preconditioner on the padded lattice
   const void* x;       // input vector (T); M_TRANSR: r
   const void* x2;      // M_TRANSR: q;  M_RESID: right-hand side (float)
   void* y;             // output vector
@@ -196,7 +198,11 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 // parity; T the transport part of A, (T x) on those rows reads only the other
 // parity of x):
 //   M_ODD_W    y_o = -(T x)_o / d_o            (x even: p_e)
+//              [NORM: <x_e, D_e x_e> + <y_o, D_o y_o> = <p_e, S p_e>]
 //   M_EVEN_S   y_e = d_e x_e + (T x)_e         [<x_e, y_e>]  (x odd: w_o)
+//   M_EVEN_SR  q_e = d_e x_e + (T x)_e, y_e -= alpha q_e   (y: the PCG
+//              residual r; m: the bfloat16 preconditioner)
+//              [<y_e, m y_e>, <y_e, y_e>]
 //   M_EVEN_RHS y_e = x2_e - (T x)_e            (x odd: D_o^-1 r_o; x2: r)
 //   M_ODD_BACK y_o = (x2_o - (T x)_o) / d_o    (x even: d_e; x2: r)
 //   M_EVEN_JAC y_e = 1 / (d_e + sum over the row's transport entries (T)_ij^2 x_j)
@@ -222,7 +228,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
   TO* __restrict__ Y = static_cast<TO*>(a.y);
   TO* __restrict__ Y2 = static_cast<TO*>(a.y2);
   T alpha = T(0);
-  if constexpr (MODE == M_TRANSR || MODE == M_SUPD) alpha = T(a.st->alpha);
+  if constexpr (MODE == M_TRANSR || MODE == M_SUPD || MODE == M_EVEN_SR) alpha = T(a.st->alpha);
   const T tinvh = T(a.tsign * a.invh);
   const T invh2 = T(a.invh * a.invh);
   const long long cs = a.cs;
@@ -317,7 +323,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
   // rows' own values
   constexpr int kRows = mode_rows(MODE);
   constexpr auto in_window = [](int K) constexpr {
-    return kRows == 0 || class_parity(cls_id(K)) != kRows - 1 || MODE == M_EVEN_S;
+    return kRows == 0 || class_parity(cls_id(K)) != kRows - 1 || MODE == M_EVEN_S || MODE == M_EVEN_SR;
   };
   {  // lanes past the last column recompute column 0 and store nothing
     T cur[NC], nb[NC];
@@ -398,7 +404,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
           // M_SUPD: the class's old outputs are loaded before its differences
           // are formed, so their latency hides behind that work
           T yold[NC];
-          if constexpr (MODE == M_SUPD) {
+          if constexpr (MODE == M_SUPD || MODE == M_EVEN_SR) {
             sfor<NC>([&](auto Kc) {
               constexpr int K = decltype(Kc)::value;
               if constexpr (cls_id(K) == c) yold[K] = T(ldb(Y + cbase(K, zo), oo));
@@ -465,9 +471,15 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
                   out = q - out;
                   cn1 = fmadd<T>(q, q, cn1);
                 }
-                if constexpr (MODE == M_SUPD) out = fmadd<T>(-alpha, out, yold[K]);
+                if constexpr (MODE == M_SUPD || MODE == M_EVEN_SR) out = fmadd<T>(-alpha, out, yold[K]);
                 stb(Y + base, oo, TO(out));
-                if constexpr (MODE == M_EVEN_S) cn0 = fmadd<T>(cur[K], out, cn0);
+                if constexpr (MODE == M_EVEN_SR) {
+                  const T mk = T(__uint_as_float((uint32_t)ldb(a.m16 + base, o / (unsigned)sizeof(T) * 2u) << 16));
+                  cn0 = fmadd<T>(mk * out, out, cn0);
+                  cn1 = fmadd<T>(out, out, cn1);
+                } else if constexpr (MODE == M_ODD_W) {
+                  cn0 = fmadd<T>(dg * out, out, cn0);  // <w_o, D_o w_o>
+                } else if constexpr (MODE == M_EVEN_S) cn0 = fmadd<T>(cur[K], out, cn0);
                 else if constexpr (NORM && MODE != M_APPLY_EQ && MODE != M_EQS) cn0 = fmadd<T>(out, out, cn0);
                 if constexpr (MODE == M_TRANSR) {
                   stb(Y2 + base, oo, TO(cur[K]));
@@ -476,10 +488,26 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const int L) 
               }
             });
             if constexpr (NORM) nrm0 += double(cn0);
-            if constexpr (MODE == M_TRANSR || MODE == M_RESID) nrm1 += double(cn1);
+            if constexpr (MODE == M_TRANSR || MODE == M_RESID || MODE == M_EVEN_SR) nrm1 += double(cn1);
           }
         }
       });
+      // M_ODD_W: <p_e, D_e p_e> over this thread's even points of the plane
+      // (with <w_o, D_o w_o> above: <p, S p>, since T_oe = -T_eo^T)
+      if constexpr (MODE == M_ODD_W && NORM) {
+        T ce = T(0);
+        sfor<NC>([&](auto Kc) {
+          constexpr int K = decltype(Kc)::value;
+          constexpr int c = cls_id(K);
+          if constexpr (class_parity(c) == 0) {
+            constexpr int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+            const bool okk = act && (cx || okx0) && (cy || oky0) && (cz || okz0);
+            const T dg = fmadd<T>(T(a.omg[band_of(K)]), css[c], csa[c]);
+            ce = okk ? fmadd<T>(dg * cur[K], cur[K], ce) : ce;
+          }
+        });
+        nrm0 += double(ce);
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) { msa[q] = msa[4 + q]; mss[q] = mss[4 + q]; }
     }
@@ -921,10 +949,10 @@ __device__ __forceinline__ float4 ld_bf4(const uint2* p) {
 }
 
 // OP 0 (init):    p = m r                              [<r, m r>, <r, r>]
-// OP 1 (r):       r -= alpha q                         [<r, m r>, <r, r>]
 // OP 2 (x, p):    x += alpha p, p = m r + beta p
-// (x is advanced together with p, one pass later than r: alpha is still the
-// step of this iteration there, and that pass runs after the stop test too)
+// (x is advanced together with p, one pass after r -- which the even-row
+// stencil pass updates: alpha is still the step of this iteration there, and
+// that pass runs after the stop test too)
 template <int OP>
 __global__ void __launch_bounds__(kBlock) k_pcg_vec(float* __restrict__ x, float* __restrict__ r,
                                                     float* __restrict__ p, const float* __restrict__ q,
@@ -938,18 +966,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_vec(float* __restrict__ x, float
   float4* x4 = reinterpret_cast<float4*>(x + base);
   float4* r4 = reinterpret_cast<float4*>(r + base);
   float4* p4 = reinterpret_cast<float4*>(p + base);
-  const float4* q4 = reinterpret_cast<const float4*>(q + base);
   const uint2* m4 = reinterpret_cast<const uint2*>(m + base);
   double s0 = 0.0, s1 = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride) {
     float4 rv = ld_nt(r4 + i);
     const float4 mv = ld_bf4(m4 + i);
-    if constexpr (OP == 1) {
-      const float4 qv = ld_nt(q4 + i);
-      rv.x = __fmaf_rn(-al, qv.x, rv.x); rv.y = __fmaf_rn(-al, qv.y, rv.y);
-      rv.z = __fmaf_rn(-al, qv.z, rv.z); rv.w = __fmaf_rn(-al, qv.w, rv.w);
-      st_nt(r4 + i, rv);
-    }
     if constexpr (OP == 2) {
       float4 pv = ld_nt(p4 + i), xv = ld_nt(x4 + i);
       xv.x = __fmaf_rn(al, pv.x, xv.x); xv.y = __fmaf_rn(al, pv.y, xv.y);

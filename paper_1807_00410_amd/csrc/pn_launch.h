@@ -19,11 +19,12 @@ enum Kind {
   K_F32_APPLY_EQ = 7,// float: y = W A x (row-equilibrated CG)
   K_F32_EQS = 8,     // float: y = W x
   // float, even-parity Schur complement (one band parity of rows)
-  K_F32_ODD_W = 9, K_F32_EVEN_S = 10, K_F32_EVEN_RHS = 11, K_F32_ODD_BACK = 12, K_F32_EVEN_JAC = 13
+  K_F32_ODD_W = 9, K_F32_EVEN_S = 10, K_F32_EVEN_RHS = 11, K_F32_ODD_BACK = 12, K_F32_EVEN_JAC = 13,
+  K_F32_EVEN_SR = 14
 };
 
 // modes whose kernels never reduce (instantiated without partial sums only)
-constexpr bool mode_no_norm(int m) { return m == M_ODD_W || m == M_EVEN_RHS || m == M_ODD_BACK || m == M_EVEN_JAC; }
+constexpr bool mode_no_norm(int m) { return m == M_EVEN_RHS || m == M_ODD_BACK || m == M_EVEN_JAC; }
 
 template <int N, typename T, int MODE, typename TO>
 hipError_t launch_flavour(bool gen, bool norm, const StencilArgs& a, hipStream_t s) {
@@ -53,7 +54,8 @@ hipError_t launch_order(int kind, bool gen, bool norm, const StencilArgs& a, hip
     case K_F32_SUPD: return launch_flavour<N, float, M_SUPD, float>(gen, true, a, s);
     case K_F32_APPLY_EQ: return launch_flavour<N, float, M_APPLY_EQ, float>(gen, true, a, s);
     case K_F32_EQS: return launch_flavour<N, float, M_EQS, float>(gen, true, a, s);
-    case K_F32_ODD_W: return launch_flavour<N, float, M_ODD_W, float>(gen, false, a, s);
+    case K_F32_ODD_W: return launch_flavour<N, float, M_ODD_W, float>(gen, true, a, s);
+    case K_F32_EVEN_SR: return launch_flavour<N, float, M_EVEN_SR, float>(gen, true, a, s);
     case K_F32_EVEN_S: return launch_flavour<N, float, M_EVEN_S, float>(gen, true, a, s);
     case K_F32_EVEN_RHS: return launch_flavour<N, float, M_EVEN_RHS, float>(gen, false, a, s);
     case K_F32_ODD_BACK: return launch_flavour<N, float, M_ODD_BACK, float>(gen, false, a, s);

@@ -133,13 +133,13 @@ class Solver:
         return rel.value
 
     KERNELS = {"apply": 0, "apply_t": 1, "apply_eq": 2, "supd": 3, "update": 4,
-               "odd_w": 5, "even_s": 6, "pcg_r": 7, "pcg_xp": 8}
+               "odd_w": 5, "even_r": 6, "pcg_xp": 7}
 
     def bench_kernel(self, kernel, iters=20):
         """Mean milliseconds of one launch of a Krylov-loop kernel in its
         in-loop form (pn_bench_kernel): "apply", "apply_t", "apply_eq",
-        "supd", "update" (the normal-equation loop) or "odd_w", "even_s",
-        "pcg_r", "pcg_xp" (the even-parity loop)."""
+        "supd", "update" (the normal-equation loop) or "odd_w",
+        "even_r", "pcg_xp" (the even-parity loop)."""
         ms = C.c_double()
         self._check(self.lib.pn_bench_kernel(self.ctx, self.KERNELS[kernel], int(iters), C.byref(ms)))
         return ms.value
