@@ -134,6 +134,11 @@ pn_status pn_net_features(pn_ctx* ctx, const float* src, uint16_t* x);
  * the lattice point with the cell's indices, divided by the largest |L00|
  * over the cells; zero where there is none.  On the context's stream. */
 pn_status pn_net_targets(pn_ctx* ctx, const double* solution, uint16_t* t);
+/* The same for the difference solution - sub (both device FP64 vectors in
+ * the packed layout; sub NULL: none): the target of a correction step, the
+ * remaining correction x* - x_j of a partially converged iterate x_j.  On the
+ * context's stream. */
+pn_status pn_net_targets_diff(pn_ctx* ctx, const double* solution, const double* sub, uint16_t* t);
 /* Attaches a network to a solver context (NULL detaches); pn_solve uses it
  * as opts->learned asks, on the solver's stream (the network's own stream is
  * restored afterwards).  The network must outlive the attachment. */

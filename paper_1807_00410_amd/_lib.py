@@ -134,6 +134,7 @@ NN_SIGNATURES = [
     ("pn_net_grid", _I, [_V, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
     ("pn_net_features", _I, [_V, _V, _V]),
     ("pn_net_targets", _I, [_V, _V, _V]),
+    ("pn_net_targets_diff", _I, [_V, _V, _V, _V]),
     ("pn_attach_net", _I, [_V, _V]),
 ]
 

@@ -1050,19 +1050,23 @@ extern "C" pn_status pn_net_features(pn_ctx* c, const float* src, uint16_t* x) {
   return launch_features(c, src, net_geom(c, false), x, c->stream);
 }
 
-extern "C" pn_status pn_net_targets(pn_ctx* c, const double* sol, uint16_t* t) {
+extern "C" pn_status pn_net_targets_diff(pn_ctx* c, const double* sol, const double* sub, uint16_t* t) {
   if (!c) return PN_ERR_ARG;
   if (!sol || !t) return fail(c, PN_ERR_ARG, "solution or t is NULL");
   pn_status e = ensure_small_net_bufs(c);
   if (e != PN_OK) return e;
   const NetGeom g = net_geom(c, false);
   const int nb = cells_grid(g);
-  hipLaunchKernelGGL(k_coef0_absmax, dim3(nb), dim3(kBlock), 0, c->stream, sol, g, c->sq_part);
+  hipLaunchKernelGGL(k_coef0_absmax, dim3(nb), dim3(kBlock), 0, c->stream, sol, sub, g, c->sq_part);
   const long long n = (long long)g.nx8 * g.ny8 * g.nz8 * kNetOut;
-  hipLaunchKernelGGL(k_net_targets, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, sol, g,
+  hipLaunchKernelGGL(k_net_targets, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, sol, sub, g,
                      (const double*)c->sq_part, nb, t);
   PN_HIP(hipGetLastError());
   return PN_OK;
+}
+
+extern "C" pn_status pn_net_targets(pn_ctx* c, const double* sol, uint16_t* t) {
+  return pn_net_targets_diff(c, sol, nullptr, t);
 }
 
 template <typename T>

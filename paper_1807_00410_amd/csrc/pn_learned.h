@@ -104,14 +104,17 @@ static __global__ void __launch_bounds__(kBlock) k_net_to_lattice(const float* _
 
 // max |coefficient 0| of an FP64 lattice vector over the cells (FP64 block
 // partial maxima).
-static __global__ void __launch_bounds__(kBlock) k_coef0_absmax(const double* __restrict__ u, const NetGeom g,
+// (u - sub when sub != NULL)
+static __global__ void __launch_bounds__(kBlock) k_coef0_absmax(const double* __restrict__ u,
+                                                                const double* __restrict__ sub, const NetGeom g,
                                                                 double* __restrict__ partial) {
   __shared__ double red[kBlock];
   double s = 0.0;
   const long long n = (long long)g.nx * g.ny * g.nz;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
     const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
-    s = fmax(s, fabs(u[lat(g, 0, x, y, z)]));
+    const long long j = lat(g, 0, x, y, z);
+    s = fmax(s, fabs(u[j] - (sub != nullptr ? sub[j] : 0.0)));
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -123,8 +126,10 @@ static __global__ void __launch_bounds__(kBlock) k_coef0_absmax(const double* __
 }
 
 // Training target [cells8][kNetOut] (bfloat16) from an FP64 lattice
-// solution, divided by max |coefficient 0| (block maxima in `partial`).
-static __global__ void __launch_bounds__(kBlock) k_net_targets(const double* __restrict__ u, const NetGeom g,
+// solution u (minus sub when sub != NULL: a remaining correction), divided by
+// max |coefficient 0| (block maxima in `partial`).
+static __global__ void __launch_bounds__(kBlock) k_net_targets(const double* __restrict__ u,
+                                                               const double* __restrict__ sub, const NetGeom g,
                                                                const double* __restrict__ partial, int nparts,
                                                                uint16_t* __restrict__ t) {
   double mx = 0.0;
@@ -137,7 +142,7 @@ static __global__ void __launch_bounds__(kBlock) k_net_targets(const double* __r
     const int x = (int)(c % g.nx8), y = (int)((c / g.nx8) % g.ny8), z = (int)(c / ((long long)g.nx8 * g.ny8));
     float v = 0.f;
     if (k < g.nk && x < g.nx && y < g.ny && z < g.nz)
-      v = (float)(u[lat(g, k, x, y, z)] * sc);
+      v = (float)((u[lat(g, k, x, y, z)] - (sub != nullptr ? sub[lat(g, k, x, y, z)] : 0.0)) * sc);
     t[i] = nn::f2bf(v);
   }
 }

@@ -113,7 +113,7 @@ def generate_corrections(n=64, nmedia=64, nrhs=8, seed0=5000, stages=(1e-2, 1e-4
                 for xj in parts:
                     s.residual64(b, xj, r)
                     X[k] = s.net_features(r.float())[0]
-                    T[k] = s.net_targets(xs - xj)[0]
+                    T[k] = s.net_targets(xs, sub=xj)[0]
                     k += 1
             s.close()
             if k % (nrhs * len(stages) * 16) == 0:

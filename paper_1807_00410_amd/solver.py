@@ -166,10 +166,14 @@ class Solver:
         self._check(self.lib.pn_net_features(self.ctx, _ptr(src, torch.float32), C.c_void_p(x.data_ptr())))
         return x
 
-    def net_targets(self, sol):
+    def net_targets(self, sol, sub=None):
+        """Training target of a packed FP64 solution (of sol - sub when sub is
+        given: the remaining correction of a partial iterate)."""
         nx8, ny8, nz8 = self.net_grid()
         t = torch.empty((1, nz8, ny8, nx8, 16), dtype=torch.bfloat16, device=sol.device)
-        self._check(self.lib.pn_net_targets(self.ctx, _ptr(sol, torch.float64), C.c_void_p(t.data_ptr())))
+        self._check(self.lib.pn_net_targets_diff(self.ctx, _ptr(sol, torch.float64),
+                                                 _ptr(sub, torch.float64) if sub is not None else None,
+                                                 C.c_void_p(t.data_ptr())))
         return t
 
     def autotune(self, iters=10):

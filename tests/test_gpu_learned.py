@@ -143,3 +143,17 @@ def test_trained_network_gain_on_held_out_medium():
     assert d < 1e-6
     s.close()
     net.close()
+
+
+def test_targets_of_a_difference_match_targets_of_the_difference():
+    # the correction targets (x* - x_j) are formed inside the library
+    m = config_p3_fbm(n=12, seed=5, order=3)
+    s = solver(m)
+    rng = np.random.default_rng(1)
+    a = torch.as_tensor(rng.normal(size=s.n), dtype=torch.float64).cuda()
+    b = torch.as_tensor(rng.normal(size=s.n), dtype=torch.float64).cuda()
+    t1 = s.net_targets(a, sub=b)
+    t2 = s.net_targets(a - b)
+    assert torch.equal(t1, t2)
+    assert torch.equal(s.net_targets(a, sub=None), s.net_targets(a))
+    s.close()
