@@ -233,6 +233,29 @@ pn_status pn_apply(pn_ctx* ctx, const float* x, float* y, int transpose);
  * solve does not use S).  Asynchronous on the context stream. */
 pn_status pn_apply_schur(pn_ctx* ctx, const float* x, float* y);
 
+/* Single-scattered light of a point light folded into the emission term
+ * (section "Rendering"): writes rhs (DEVICE FP32, packed layout, n_unknowns
+ * entries) with, at the location y of every unknown (coefficient k = (l, m)),
+ *   Q^{l,m}(y) = sigma_s(y) power exp(-tau) / (4 pi r^2) g^l Y_R^{l,m}(w),
+ * the in-scattered uncollided light: r = |y - light| (at least h / 2), w =
+ * (y - light) / r, tau = the optical depth of the segment light -> y through
+ * the thresholded extinction of the cells (constant per cell, zero outside
+ * the grid), sigma_s the mean of the cells adjacent to y, and g^l Y_R^{l,m}(w)
+ * the projection of the Henyey-Greenstein phase function.  light: HOST array
+ * of 3 physical coordinates (the grid spans [0, n_d h] along axis d; the light
+ * may lie outside).  Solving with this right-hand side gives the
+ * multiple-scattered light.  PN_ERR_ARG on a periodic axis or non-finite
+ * arguments.  Asynchronous on the context stream. */
+pn_status pn_single_scatter(pn_ctx* ctx, const double* light, double power, float* rhs);
+
+/* Un-staggering (section "Rendering"): every coefficient of the solution x
+ * (DEVICE FP64, packed layout) interpolated to the voxel centres -- its own
+ * lattice point along an axis where its class is centred, the mean of the
+ * cell's two faces where it sits on faces (face n is face 0 on a periodic
+ * axis); the extra boundary coefficients are dropped.  out: DEVICE FP32
+ * [ncoeff][nz][ny][nx].  Asynchronous on the context stream. */
+pn_status pn_unstagger(pn_ctx* ctx, const double* x, float* out);
+
 /* Row weights of the equilibrated CG variant (PN_VARIANT_CG_EQ): w[i] =
  * 1 / (d_i^2 + sum of the squared transport entries of row i with every
  * neighbour present), d_i the diagonal -- 1 / ||row i of A||_2^2 away from

@@ -80,6 +80,8 @@ SIGNATURES = [
     ("pn_bench_kernel", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     ("pn_row_weights", C.c_int, [C.c_void_p, C.c_void_p]),
     ("pn_apply_schur", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pn_single_scatter", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_double, C.c_void_p]),
+    ("pn_unstagger", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pn_set_tiles", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     ("pn_get_tiles", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("pn_coupling_table", C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),

@@ -16,6 +16,7 @@
 
 #include "../../include/pn.h"
 #include "pn_internal.h"
+#include "pn_render.h"
 #include "pn_learned.h"
 
 
@@ -582,6 +583,53 @@ extern "C" pn_status pn_apply(pn_ctx* c, const float* x, float* y, int transpose
 }
 
 static bool schur_ok(const pn_ctx* c);
+
+static RenderArgs render_args(const pn_ctx* c) {
+  RenderArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nc = c->nc; a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
+  for (int d = 0; d < 3; ++d) a.per[d] = c->bcs[d] == BC_PERIODIC;
+  for (int k = 0; k < c->nc; ++k) {
+    a.off[k] = c->off[k];
+    for (int d = 0; d < 3; ++d) { a.ext[k][d] = c->ext[k][d]; a.cls[k][d] = c->cls[k][d]; }
+  }
+  a.h = c->h;
+  a.g = (double)c->g;
+  a.med = c->med;
+  return a;
+}
+
+static int render_grid(long long n) {
+  long long b = (n + kBlock - 1) / kBlock;
+  return (int)std::max<long long>(1, std::min<long long>(b, 4096));
+}
+
+extern "C" pn_status pn_single_scatter(pn_ctx* c, const double* light, double power, float* rhs) {
+  if (!c) return PN_ERR_ARG;
+  if (!light || !rhs) return fail(c, PN_ERR_ARG, "light or rhs is NULL");
+  if (!std::isfinite(light[0]) || !std::isfinite(light[1]) || !std::isfinite(light[2]) || !std::isfinite(power))
+    return fail(c, PN_ERR_ARG, "light position and power must be finite");
+  if (c->bcs[0] == BC_PERIODIC || c->bcs[1] == BC_PERIODIC || c->bcs[2] == BC_PERIODIC)
+    return fail(c, PN_ERR_ARG, "single scattering needs a non-periodic domain");
+  RenderArgs a = render_args(c);
+  for (int d = 0; d < 3; ++d) a.light[d] = light[d];
+  a.power = power;
+  long long maxsz = 0;
+  for (int k = 0; k < c->nc; ++k) maxsz = std::max<long long>(maxsz, (long long)c->ext[k][0] * c->ext[k][1] * c->ext[k][2]);
+  hipLaunchKernelGGL(k_single_scatter, dim3(render_grid(maxsz), c->nc), dim3(kBlock), 0, c->stream, a, rhs);
+  PN_HIP(hipGetLastError());
+  return PN_OK;
+}
+
+extern "C" pn_status pn_unstagger(pn_ctx* c, const double* x, float* out) {
+  if (!c) return PN_ERR_ARG;
+  if (!x || !out) return fail(c, PN_ERR_ARG, "x or out is NULL");
+  const RenderArgs a = render_args(c);
+  const long long cells = (long long)c->nx * c->ny * c->nz;
+  hipLaunchKernelGGL(k_unstagger, dim3(render_grid(cells), c->nc), dim3(kBlock), 0, c->stream, a, x, out);
+  PN_HIP(hipGetLastError());
+  return PN_OK;
+}
 
 extern "C" pn_status pn_apply_schur(pn_ctx* c, const float* x, float* y) {
   if (!c) return PN_ERR_ARG;

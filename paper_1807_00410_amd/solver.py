@@ -109,6 +109,22 @@ class Solver:
         self._check(self.lib.pn_apply(self.ctx, _ptr(x, torch.float32), _ptr(y, torch.float32), int(transpose)))
         return y
 
+    def single_scatter(self, light, power=1.0, out=None):
+        """Packed FP32 right-hand side of the single-scattered light of a point
+        light at `light` (physical coordinates) with `power` (pn_single_scatter)."""
+        q = torch.empty(self.n, dtype=torch.float32, device="cuda") if out is None else out
+        pos = (C.c_double * 3)(*[float(v) for v in light])
+        self._check(self.lib.pn_single_scatter(self.ctx, pos, float(power), _ptr(q, torch.float32)))
+        return q
+
+    def unstagger(self, x):
+        """[ncoeff, nz, ny, nx] FP32 coefficients at the voxel centres of the
+        packed FP64 solution x (pn_unstagger)."""
+        nx, ny, nz = self.layout.dims
+        out = torch.empty((self.layout.ncoeff, nz, ny, nx), dtype=torch.float32, device=x.device)
+        self._check(self.lib.pn_unstagger(self.ctx, _ptr(x, torch.float64), C.c_void_p(out.data_ptr())))
+        return out
+
     def apply_schur(self, x, y=None):
         """y_o = -D_o^-1 T_oe x_e and y_e = S x_e (pn_apply_schur); x packed FP32."""
         y = torch.empty_like(x) if y is None else y
