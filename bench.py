@@ -225,8 +225,78 @@ def extra_configs(args):
         out["p3_96_heldout"] = r
         print("[bench] P3 96^3 held-out: plain %.3fs, guess %.3fs" % (sec, r["guess"]["seconds"]), file=sys.stderr,
               flush=True)
+    out.update(validation_workloads(args))
     # the batched workload
     out["batch"] = bench_batch(args, quiet=True)
+    return out
+
+
+def validation_workloads(args):
+    """The validation problems of section "Results": the 2D checkerboard
+    (P1-P5, 71 x 71 cells, to the residual 1e-10 the paper quotes) and the 80^3
+    point source (P1-P5, to the same residual; its P1 fluence against the
+    oracle's CDA solution).  Optionally writes the fluence along the x axis
+    through the source for every order and the CDA."""
+    import numpy as np
+    import torch
+    from oracle.assemble import assemble, rhs_isotropic
+    from oracle.cda import cda_solve
+    from oracle.solve import direct
+    from oracle.stagger import Layout
+    from synth import config_checkerboard, config_point_source
+    from paper_1807_00410_amd.solver import Solver
+    dev = torch.device("cuda:0")
+    tol = 1e-10
+    paper_cb = {1: 0.27, 5: 25.0}           # seconds on the paper's CPU (hardware not stated)
+    paper_ps = {1: 600.0, 5: 2700.0}
+    out = {"checkerboard_71": {}, "point_source_80": {}}
+    lines = {}
+    for name, mk_cfg in (("checkerboard_71", lambda o: config_checkerboard(o, n=71)),
+                         ("point_source_80", lambda o: config_point_source(o, n=80))):
+        for order in range(1, 6):
+            m = mk_cfg(order)
+            s = Solver(m.order, m.dims, torch.as_tensor(m.sigma_t).to(dev), torch.as_tensor(m.albedo).to(dev),
+                       g=m.g, sigma_t_min=m.sigma_t_min, bc=m.bc, h=m.h)
+            rhs = s.rhs_from_q00(torch.as_tensor(m.q00[0]).to(dev))
+            x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+            sec, info = timed_solve(s, rhs, x, tol=tol, inner_tol=args.inner_tol)
+            xs = x.cpu().numpy()
+            s.close()
+            r = {"seconds": sec, "iters": info["inner_iters"], "outer_iters": info["outer_iters"],
+                 "rel_residual": info["rel_residual"], "unknowns": int(xs.size)}
+            paper = (paper_cb if name.startswith("checker") else paper_ps).get(order)
+            if paper is not None:
+                r["paper_seconds_cpu"] = paper
+            lay = Layout(m.order, m.dims, m.bc)
+            if name.startswith("checker") and order <= 3:
+                A, _ = assemble(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min, bc=m.bc, h=m.h)
+                r["rel_l2_vs_oracle"] = rel_l2(xs, direct(A, rhs_isotropic(lay, m.q00[0])))
+                r["oracle"] = "SuperLU"
+            if name.startswith("point"):
+                c = m.dims[0] // 2
+                lines["P%d" % order] = lay.view(xs, 0)[c, c, c:].copy()
+                if order == 1:
+                    phi = cda_solve(m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min, m.q00[0])
+                    r["rel_l2_vs_cda"] = rel_l2(lay.view(xs, 0), phi)
+                    lines["CDA"] = phi[c, c, c:].copy()
+            out[name]["P%d" % order] = r
+            print("[bench] %s P%d: %.4fs iters %d" % (name, order, sec, info["inner_iters"]), file=sys.stderr,
+                  flush=True)
+    out["checkerboard_71"]["workload"] = ("2D checkerboard, 7 x 7 unit blocks on 71 x 71 cells (one z-periodic "
+                                          "cell), absorbers sigma_a 10, scatterers sigma_s 1, central unit "
+                                          "source; to %g" % tol)
+    out["point_source_80"]["workload"] = ("point source, 80^3 cells of size 1/80, sigma_t 8, albedo 0.9, "
+                                          "isotropic, Q00 = 1 in the central 2^3 cells; to %g" % tol)
+    if args.lineplot:
+        with open(args.lineplot, "w") as f:
+            f.write("# Point source 80^3: fluence coefficient L00 along +x through the source\n\n")
+            f.write("Cells (40..79, 40, 40); sigma_t 8, albedo 0.9, isotropic; every order solved to the "
+                    "relative residual 1e-10; CDA by the oracle.\n\nCommand: `python bench.py --no-cpu-baseline "
+                    "--lineplot %s`\n\n" % os.path.relpath(args.lineplot, ROOT))
+            keys = ["P1", "CDA", "P2", "P3", "P4", "P5"]
+            f.write("| r / h | " + " | ".join(keys) + " |\n|" + "---|" * (len(keys) + 1) + "\n")
+            for i in range(len(lines["P1"])):
+                f.write("| %.1f | " % (i + 0.5) + " | ".join("%.6e" % lines[k][i] for k in keys) + " |\n")
     return out
 
 
@@ -378,6 +448,8 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1807_00410_amd", "weights", "unet_p3.bin"))
     ap.add_argument("--workload", choices=("p5", "batch"), default="p5")
     ap.add_argument("--batch-media", type=int, default=48)
+    ap.add_argument("--lineplot", default=None, metavar="PATH",
+                    help="write the point-source fluence along +x for P1-P5 and the CDA as a markdown table")
     ap.add_argument("--profile-kernels", default=None, metavar="LIST",
                     help="profiling mode: comma-separated loop kernels (apply, apply_t, odd_w, even_r, pcg_xp, "
                          "apply_eq, supd, update) "

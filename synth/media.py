@@ -110,7 +110,8 @@ class Medium:
     g: float
     sigma_t_min: float
     q00: List[np.ndarray] = field(default_factory=list)   # one emission field per RHS
-    bc: int = 0                                            # 0 vacuum, 1 periodic
+    bc: object = 0                                         # 0 vacuum, 1 periodic, 2 Neumann, or one per axis
+    h: float = 0.0                                         # cell size (0: 1 / n_x)
 
     def __post_init__(self):
         # scalars are FP32 inputs like the fields
@@ -234,3 +235,49 @@ def config_small(order, dims, seed=0, sigma_range=(0.5, 20.0), albedo_range=(0.5
     qs = [_f32(rng.uniform(0.0, 1.0, size=shp)) for _ in range(nrhs)]
     return Medium("small_p%d_%dx%dx%d_s%d" % ((order,) + tuple(dims) + (seed,)), order, tuple(dims),
                   _f32(st), _f32(alb), g, sigma_t_min, qs, bc=bc)
+
+
+def checkerboard_blocks():
+    """Block kinds of the 7 x 7 checkerboard (lattice) problem, indexed
+    [block_y, block_x]: 1 = purely absorbing (sigma_a = 10), 2 = the
+    isotropic unit source (purely scattering), 0 = purely scattering
+    (sigma_s = 1).  Absorbers sit on the blocks (i, j) of the inner 5 x 5 with
+    i + j even, the central block holds the source instead."""
+    kind = np.zeros((7, 7), dtype=np.int64)
+    for j in range(1, 6):
+        for i in range(1, 6):
+            if (i + j) % 2 == 0:
+                kind[j, i] = 1
+    kind[3, 3] = 2
+    return kind
+
+
+def config_checkerboard(order, n=71, size=7.0):
+    """2D checkerboard: a size x size domain of unit blocks on n x n cells
+    (a cell takes the block containing its centre), z-invariant (one
+    z-periodic cell), vacuum in x and y, isotropic scattering.  Absorbing
+    blocks: sigma_t = 10, albedo 0; other blocks: sigma_t = 1, albedo 1;
+    Q^{0,0} = 1 in the central block."""
+    kind = checkerboard_blocks()
+    h = size / n
+    c = (np.arange(n) + 0.5) * h
+    b = np.minimum(np.floor(c).astype(np.int64), int(size) - 1)
+    k2 = kind[b[:, None], b[None, :]]                     # [y, x]
+    st = np.where(k2 == 1, 10.0, 1.0)[None]
+    alb = np.where(k2 == 1, 0.0, 1.0)[None]
+    q = (k2 == 2).astype(np.float64)[None]
+    return Medium("checkerboard_p%d_%d" % (order, n), order, (n, n, 1), _f32(st), _f32(alb), 0.0, 0.0, [_f32(q)],
+                  bc=(0, 0, 1), h=h)
+
+
+def config_point_source(order, n=80, sigma_t=8.0, albedo=0.9, g=0.0):
+    """Point source in a homogeneous medium: n^3 cells of size 1/n, sigma_t =
+    8, albedo 0.9, isotropic scattering, Q^{0,0} = 1 in the central 2^3 cells
+    (n even), vacuum boundary."""
+    if n % 2:
+        raise ValueError("the point source needs an even n")
+    q = np.zeros((n, n, n))
+    c = n // 2
+    q[c - 1:c + 1, c - 1:c + 1, c - 1:c + 1] = 1.0
+    return Medium("point_source_p%d_%d" % (order, n), order, (n, n, n), _f32(np.full((n, n, n), sigma_t)),
+                  _f32(np.full((n, n, n), albedo)), g, 0.0, [_f32(q)])
