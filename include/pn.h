@@ -106,7 +106,7 @@ typedef struct {
   double inner_tol;   /* relative reduction of the inner FP32 residual         */
   int use_guess;      /* 0: start from x = 0; 1: start from the x passed in    */
   int graph_iters;    /* Krylov iterations per captured HIP graph launch       */
-  int variant;        /* PN_VARIANT_AUTO, _CGLS, _CG or _CG_EQ (see below)     */
+  int variant;        /* PN_VARIANT_AUTO, _CGLS, _CG, _CG_EQ, _SCHUR, _SCHUR_MG */
   int learned;        /* PN_LEARNED_* (needs a network, pn_attach_net in pn_nn.h) */
 } pn_solve_opts;
 
@@ -138,6 +138,17 @@ typedef struct {
  * applies A once (odd rows from the even part, then even rows), where CG on
  * the normal equations applies A and A^T.  PN_ERR_ARG with a Neumann axis, with
  * zero extinction in some cell (D_o singular: raise sigma_t_min) or PN_FP64.
+ * SCHUR_MG: the same PCG with a multigrid preconditioner in place of the
+ * Jacobi one.  S couples every even coefficient to itself only at the six
+ * lattice neighbours (a weighted diffusion operator per coefficient, the
+ * band-l form of the diffusion equation that P1 collapses to, section
+ * "Results"), so B r = 0.7 M r + P V(P^T r): M the Jacobi inverse diagonal,
+ * P the piecewise-constant prolongation over 2 x 2 x 2 aggregates of each
+ * coefficient's lattice and V one V-cycle on the Galerkin coarse operators
+ * (damped Jacobi smoothing, coarsening down to at most 5 points per axis).
+ * B is symmetric positive definite and formed per solve from the medium;
+ * the solution is the same, only the iteration count changes.  Needs the
+ * vacuum boundary on every axis (PN_ERR_ARG otherwise).
  * CGLS: the residual-based CGLS
  * form (r <- r - alpha q fused into s = A^T r).  CG: CG on the normal
  * equations A^T A u = A^T Q with the recursive normal residual
@@ -148,8 +159,9 @@ typedef struct {
  * every transport neighbour present, formed from the medium inside the
  * kernels: no extra memory traffic); the inner stop then tests the W-weighted
  * residual.  Needs the register-window stencil (PN_ERR_ARG with pn_set_tiles
- * or PN_FP64).  AUTO: SCHUR on the register-window stencil (CG_EQ when an
- * axis is Neumann or some cell has zero extinction), CG on the LDS-tiled one; the batched solve treats AUTO as
+ * or PN_FP64).  AUTO: SCHUR_MG on the register-window stencil when every axis
+ * is vacuum, else SCHUR (CG_EQ when an axis is Neumann or some cell has zero
+ * extinction), CG on the LDS-tiled one; the batched solve treats AUTO as
  * CG_EQ.  The FP64 refinement checks the true, unweighted residual
  * ||Q - A x|| in every case. */
 #define PN_VARIANT_AUTO 0
@@ -157,6 +169,7 @@ typedef struct {
 #define PN_VARIANT_CG 2
 #define PN_VARIANT_CG_EQ 3
 #define PN_VARIANT_SCHUR 4
+#define PN_VARIANT_SCHUR_MG 5
 
 #define PN_MAX_HISTORY 64
 /* Phases of a solve timed in pn_solve_info.t_ms (wall milliseconds, host

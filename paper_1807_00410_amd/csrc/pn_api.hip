@@ -13,10 +13,12 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "../../include/pn.h"
 #include "pn_internal.h"
 #include "pn_render.h"
+#include "pn_mg_kernels.h"
 #include "pn_learned.h"
 
 
@@ -175,6 +177,10 @@ static void free_all(pn_ctx* c) {
   if (c->gexec64) hipGraphExecDestroy(c->gexec64);
   if (c->gexec_cg) hipGraphExecDestroy(c->gexec_cg);
   if (c->gexec_schur) hipGraphExecDestroy(c->gexec_schur);
+  if (c->gexec_mg) hipGraphExecDestroy(c->gexec_mg);
+  hipFree(c->mg_terms);
+  hipFree(c->mg_partials);
+  for (int L = 0; L < kMgMaxLevels; ++L) { hipFree(c->mg_op[L]); hipFree(c->mg_r[L]); hipFree(c->mg_z[L]); hipFree(c->mg_zt[L]); }
   hipFree(c->med); hipFree(c->med32);
   for (int i = 0; i < 2; ++i) { hipFree(c->r32[i]); hipFree(c->r64[i]); }
   hipFree(c->m16);
@@ -304,6 +310,7 @@ extern "C" pn_status pn_autotune(pn_ctx* c, int iters, int* zchunk, double* ms) 
   if (c->gexec64) { hipGraphExecDestroy(c->gexec64); c->gexec64 = nullptr; c->giters64 = 0; }
   if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
   if (c->gexec_schur) { hipGraphExecDestroy(c->gexec_schur); c->gexec_schur = nullptr; c->giters_schur = 0; }
+  if (c->gexec_mg) { hipGraphExecDestroy(c->gexec_mg); c->gexec_mg = nullptr; c->giters_mg = 0; }
   if (zchunk) *zchunk = z;
   if (ms) *ms = bms;
   return PN_OK;
@@ -509,6 +516,7 @@ extern "C" pn_status pn_set_zchunk(pn_ctx* c, int zchunk) {
   if (c->gexec64) { hipGraphExecDestroy(c->gexec64); c->gexec64 = nullptr; c->giters64 = 0; }
   if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
   if (c->gexec_schur) { hipGraphExecDestroy(c->gexec_schur); c->gexec_schur = nullptr; c->giters_schur = 0; }
+  if (c->gexec_mg) { hipGraphExecDestroy(c->gexec_mg); c->gexec_mg = nullptr; c->giters_mg = 0; }
   return PN_OK;
 }
 
@@ -517,6 +525,7 @@ extern "C" pn_status pn_set_tiles(pn_ctx* c, int tx, int ty, int zchunk) {
   if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (c->gexec_cg) { hipGraphExecDestroy(c->gexec_cg); c->gexec_cg = nullptr; c->giters_cg = 0; }
   if (c->gexec_schur) { hipGraphExecDestroy(c->gexec_schur); c->gexec_schur = nullptr; c->giters_schur = 0; }
+  if (c->gexec_mg) { hipGraphExecDestroy(c->gexec_mg); c->gexec_mg = nullptr; c->giters_mg = 0; }
   if (tx == 0 && ty == 0) {  // back to the register-window stencil
     c->use_lds = 0;
     return PN_OK;
@@ -934,6 +943,171 @@ static bool schur_ok(const pn_ctx* c) {
   return c->bcs[0] != BC_NEUMANN && c->bcs[1] != BC_NEUMANN && c->bcs[2] != BC_NEUMANN && !c->zero_ext;
 }
 
+// ------------------------------------------------ multigrid preconditioner --
+// B r = omega_f M r + P V(P^T r) (see pn_mg.h), on contexts with the vacuum
+// boundary on every axis (aggregation over the class extents).
+constexpr float kMgOmegaFine = 0.7f;  // weight of the Jacobi part of B
+constexpr float kMgOmega = 0.7f;      // damped Jacobi on the coarse levels
+constexpr int kMgSweeps = 16;         // damped Jacobi sweeps on the coarsest level
+constexpr int kMgCoarsest = 5;        // coarsen until every axis has at most this many points
+
+static bool mg_ok(const pn_ctx* c) {
+  return schur_ok(c) && c->bcs[0] == BC_VACUUM && c->bcs[1] == BC_VACUUM && c->bcs[2] == BC_VACUUM &&
+         c->even.nk >= 1 && c->even.nk <= kMgMaxEven;
+}
+
+static long long mg_points(const MgGeom& g, int s) { return (long long)g.ext[s][0] * g.ext[s][1] * g.ext[s][2]; }
+
+static int mg_blocks(const MgGeom& g) {
+  long long m = 0;
+  for (int s = 0; s < g.nk; ++s) m = std::max(m, mg_points(g, s));
+  const long long b = (m + kBlock - 1) / kBlock;
+  return (int)std::max<long long>(1, std::min<long long>(b, 2048));
+}
+
+// Level geometry, coupling terms and buffers (once per context).
+static pn_status mg_alloc(pn_ctx* c) {
+  if (c->mg_levels > 0) return PN_OK;
+  MgFine& f = c->mg_fine;
+  std::memset(&f, 0, sizeof(f));
+  f.nk = c->even.nk; f.PX = c->PX; f.PY = c->PY; f.cs = c->cs;
+  MgGeom* g = c->mg_geom;
+  std::memset(g, 0, sizeof(MgGeom) * kMgMaxLevels);
+  g[0].nk = f.nk;
+  int slot_of[kMaxCoeff];
+  for (int k = 0; k < kMaxCoeff; ++k) slot_of[k] = -1;
+  for (int s = 0; s < f.nk; ++s) {
+    const int k = c->even.k[s];
+    f.k[s] = k;
+    slot_of[k] = s;
+    for (int d = 0; d < 3; ++d) { f.ext[s][d] = c->ext[k][d]; f.cls[s][d] = c->cls[k][d]; g[0].ext[s][d] = c->ext[k][d]; }
+    g[0].off[s + 1] = g[0].off[s] + mg_points(g[0], s);
+  }
+  int levels = 0;
+  for (;;) {
+    const MgGeom& a = g[levels];
+    MgGeom& b = g[levels + 1];
+    b.nk = a.nk;
+    int mx = 0;
+    for (int s = 0; s < a.nk; ++s) {
+      for (int d = 0; d < 3; ++d) { b.ext[s][d] = (a.ext[s][d] + 1) / 2; mx = std::max(mx, b.ext[s][d]); }
+      b.off[s + 1] = b.off[s] + mg_points(b, s);
+    }
+    ++levels;
+    if (mx <= kMgCoarsest || levels + 1 >= kMgMaxLevels) break;
+  }
+  // squared couplings of every even row per axis
+  MgTerms t;
+  std::memset(&t, 0, sizeof(t));
+  const int cap = 8192;
+  std::vector<int> tk(cap), td(cap), tkp(cap);
+  std::vector<double> tv(cap);
+  const int nt = pn_coupling_table(c->order, tk.data(), td.data(), tkp.data(), tv.data(), cap);
+  if (nt < 0 || nt > cap) return fail(c, PN_ERR_ARG, "multigrid: coupling table");
+  for (int i = 0; i < nt; ++i) {
+    const int s = slot_of[tk[i]];
+    if (s < 0) continue;
+    const int d = td[i];
+    int& n = t.n[s][d];
+    if (n >= kMgMaxTerms) return fail(c, PN_ERR_ARG, "multigrid: too many couplings of one row along one axis");
+    t.j[s][d][n] = tkp[i];
+    t.c2[s][d][n] = (float)(tv[i] * tv[i]);
+    ++n;
+  }
+  PN_HIP(hipMalloc(&c->mg_terms, sizeof(MgTerms)));
+  PN_HIP(hipMemcpy(c->mg_terms, &t, sizeof(MgTerms), hipMemcpyHostToDevice));
+  for (int L = 1; L <= levels; ++L) {
+    const size_t n = (size_t)g[L].off[g[L].nk];
+    PN_HIP(hipMalloc(&c->mg_op[L], sizeof(float4) * n));
+    PN_HIP(hipMalloc(&c->mg_r[L], sizeof(float) * n));
+    PN_HIP(hipMalloc(&c->mg_z[L], sizeof(float) * n));
+    PN_HIP(hipMalloc(&c->mg_zt[L], sizeof(float) * n));
+  }
+  c->mg_npart = levels == 1 ? 1 : mg_blocks(g[1]) * f.nk;
+  PN_HIP(hipMalloc(&c->mg_partials, sizeof(double) * 2 * c->mg_npart));
+  c->mg_levels = levels;
+  return PN_OK;
+}
+
+// Operators of every level from the fine diagonal (1 / m32 in the even
+// slots) and 1 / d_o (invdo, the odd slots).
+static pn_status mg_setup_ops(pn_ctx* c, const float* m32, const float* invdo, hipStream_t st) {
+  const MgGeom* g = c->mg_geom;
+  hipLaunchKernelGGL(k_mg_setup1, dim3(mg_blocks(g[1]), g[1].nk), dim3(kBlock), 0, st, c->mg_fine, g[1],
+                     (const MgTerms*)c->mg_terms, m32, invdo, c->h > 0.0 ? 1.0 / (c->h * c->h) : 0.0, c->mg_op[1]);
+  PN_HIP(hipGetLastError());
+  for (int L = 1; L < c->mg_levels; ++L) {
+    hipLaunchKernelGGL(k_mg_coarsen, dim3(mg_blocks(g[L + 1]), g[L + 1].nk), dim3(kBlock), 0, st, g[L], g[L + 1],
+                       (const float4*)c->mg_op[L], c->mg_op[L + 1]);
+    PN_HIP(hipGetLastError());
+  }
+  return PN_OK;
+}
+
+static const float* mg_final(const pn_ctx* c, int L) { return L == c->mg_levels ? c->mg_z[L] : c->mg_zt[L]; }
+
+// One V-cycle on P^T r (fine r: the even slots of the padded r); the level-1
+// result in mg_final(c, 1), the partials of <P^T r, V(P^T r)> in mg_partials.
+static hipError_t mg_vcycle(pn_ctx* c, const float* r, hipStream_t st) {
+  const MgGeom* g = c->mg_geom;
+  const int Lc = c->mg_levels;
+  const DevState* ds = c->st;
+  hipLaunchKernelGGL(k_mg_restrict0, dim3(mg_blocks(g[1]), g[1].nk), dim3(kBlock), 0, st, c->mg_fine, g[1], r,
+                     c->mg_r[1], ds);
+  for (int L = 1; L < Lc; ++L)
+    hipLaunchKernelGGL(k_mg_down, dim3(mg_blocks(g[L + 1]), g[L + 1].nk), dim3(kBlock), 0, st, g[L], g[L + 1],
+                       (const float4*)c->mg_op[L], (const float*)c->mg_r[L], c->mg_z[L], c->mg_r[L + 1], kMgOmega, ds);
+  hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(kFinBlock), 0, st, g[Lc], (const float4*)c->mg_op[Lc],
+                     (const float*)c->mg_r[Lc], c->mg_z[Lc], c->mg_zt[Lc], kMgSweeps, kMgOmega,
+                     Lc == 1 ? c->mg_partials : (double*)nullptr, ds);
+  for (int L = Lc - 1; L >= 1; --L)
+    hipLaunchKernelGGL(k_mg_up, dim3(mg_blocks(g[L]), g[L].nk), dim3(kBlock), 0, st, g[L], g[L + 1],
+                       (const float4*)c->mg_op[L], (const float*)c->mg_r[L], (const float*)c->mg_z[L],
+                       mg_final(c, L + 1), c->mg_zt[L], kMgOmega, L == 1 ? c->mg_partials : (double*)nullptr, ds);
+  return hipGetLastError();
+}
+
+// Even-parity PCG iteration with the multigrid preconditioner: w_o | alpha |
+// r update (<r, M r>, <r, r>) | stop test | V-cycle | beta | x, p.
+static hipError_t enqueue_iteration_mg(pn_ctx* c, hipStream_t st) {
+  StencilArgs a = base_args(c);
+  a.st = c->st;
+  a.tsign = 1.0;
+  a.partials = c->partials;
+  a.x = c->p32; a.y = c->p32;
+  hipError_t e = launch_stencil<float, M_ODD_W, float>(c, a, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fin_alpha_pcg, dim3(1), dim3(kFinBlock), 0, st, c->st, c->partials, c->nblocks);
+  a.x = c->p32; a.y = c->r32[1]; a.m16 = c->m16;
+  e = launch_stencil<float, M_EVEN_SR, float>(c, a, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fin_rz_mg<false>, dim3(1), dim3(kFinBlock), 0, st, c->st, (const double*)c->partials,
+                     c->nblocks, 0.0);
+  e = mg_vcycle(c, c->r32[1], st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fin_beta_mg<false>, dim3(1), dim3(kFinBlock), 0, st, c->st, (const double*)c->mg_partials,
+                     c->mg_npart, (double)kMgOmegaFine);
+  const dim3 vg(pcg_vec_blocks(c), c->even.nk);
+  hipLaunchKernelGGL(k_pcg_vec_mg<2>, vg, dim3(kBlock), 0, st, c->d32, (const float*)c->r32[1], c->p32,
+                     (const uint16_t*)c->m16, c->mg_fine, c->mg_geom[1], mg_final(c, 1), kMgOmegaFine,
+                     (const DevState*)c->st);
+  return hipGetLastError();
+}
+
+static pn_status build_graph_mg(pn_ctx* c, int iters, hipGraphExec_t* exec) {
+  hipGraph_t g = nullptr;
+  PN_HIP(hipStreamBeginCapture(c->sstream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < iters && e == hipSuccess; ++i) e = enqueue_iteration_mg(c, c->sstream);
+  hipError_t e2 = hipStreamEndCapture(c->sstream, &g);
+  if (e != hipSuccess) { if (g) hipGraphDestroy(g); return fail(c, PN_ERR_HIP, std::string("capture: ") + hipGetErrorString(e)); }
+  if (e2 != hipSuccess) return fail(c, PN_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
+  hipError_t e3 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e3 != hipSuccess) return fail(c, PN_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e3));
+  return PN_OK;
+}
+
 static pn_status build_graph_cg(pn_ctx* c, int iters, bool eq, hipGraphExec_t* exec) {
   hipGraph_t g = nullptr;
   PN_HIP(hipStreamBeginCapture(c->sstream, hipStreamCaptureModeThreadLocal));
@@ -1149,8 +1323,11 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
   // ping-pong, the A^T pass streams two).
   // FP32 even-parity PCG (Schur complement): SCHUR, and AUTO on the
   // register-window stencil when no axis is Neumann
+  // with the multigrid preconditioner: SCHUR_MG, and AUTO when every axis is vacuum
+  const bool mg = (sizeof(T) == 4) && mg_ok(c) && !c->use_lds &&
+                  (o.variant == PN_VARIANT_SCHUR_MG || o.variant == PN_VARIANT_AUTO);
   const bool schur = (sizeof(T) == 4) && schur_ok(c) &&
-                     (o.variant == PN_VARIANT_SCHUR || (o.variant == PN_VARIANT_AUTO && !c->use_lds));
+                     (mg || o.variant == PN_VARIANT_SCHUR || (o.variant == PN_VARIANT_AUTO && !c->use_lds));
   const bool cg = (sizeof(T) == 4) && !schur && o.variant != PN_VARIANT_CGLS;
   // row equilibration: AUTO and CG_EQ on the register-window stencil
   const bool eq = cg && !c->use_lds && (o.variant == PN_VARIANT_AUTO || o.variant == PN_VARIANT_CG_EQ);
@@ -1159,13 +1336,18 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     giters = &c->giters_cg;
   }
   if (schur) {
-    gexec = &c->gexec_schur;
-    giters = &c->giters_schur;
+    gexec = mg ? &c->gexec_mg : &c->gexec_schur;
+    giters = mg ? &c->giters_mg : &c->giters_schur;
+  }
+  if (mg) {
+    pn_status e = mg_alloc(c);
+    if (e != PN_OK) return e;
   }
   int gi = o.graph_iters < 2 ? 2 : (o.graph_iters + 1) & ~1;  // even: r ends in r0
   if (*gexec == nullptr || *giters != gi || (cg && c->gcg_eq != (int)eq)) {
     if (*gexec) { hipGraphExecDestroy(*gexec); *gexec = nullptr; }
-    pn_status e = schur ? build_graph_schur(c, gi, gexec)
+    pn_status e = mg      ? build_graph_mg(c, gi, gexec)
+                  : schur ? build_graph_schur(c, gi, gexec)
                   : cg  ? build_graph_cg(c, gi, eq, gexec)
                         : build_graph<T>(c, gi, d, p, q, s, r0, r1, gexec);
     if (e != PN_OK) return e;
@@ -1186,6 +1368,10 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(c->nv)), dim3(kBlock), 0, c->sstream, (const float*)c->s32, c->m16,
                        (long)c->nv);
     PN_HIP(hipGetLastError());
+    if (mg) {
+      pn_status e = mg_setup_ops(c, c->s32, c->q32, c->sstream);
+      if (e != PN_OK) return e;
+    }
   }
   hipStream_t ss = c->sstream;
   DevState init;
@@ -1284,8 +1470,19 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
         PN_HIP((launch_stencil<float, M_EVEN_RHS, float>(c, b, ss)));
         hipLaunchKernelGGL(k_pcg_vec<0>, vg, dim3(kBlock), 0, ss, d, r1, p, (const float*)q, (const uint16_t*)c->m16,
                            c->even, c->partials, (const DevState*)c->st);
-        hipLaunchKernelGGL(k_fin_init_pcg, dim3(1), dim3(kFinBlock), 0, ss, c->st, c->partials, (int)(vg.x * vg.y),
-                           itol * itol);
+        if (mg) {  // p = B r, gamma = <r, B r>
+          hipLaunchKernelGGL(k_fin_rz_mg<true>, dim3(1), dim3(kFinBlock), 0, ss, c->st, (const double*)c->partials,
+                             (int)(vg.x * vg.y), itol * itol);
+          PN_HIP(mg_vcycle(c, r1, ss));
+          hipLaunchKernelGGL(k_fin_beta_mg<true>, dim3(1), dim3(kFinBlock), 0, ss, c->st,
+                             (const double*)c->mg_partials, c->mg_npart, (double)kMgOmegaFine);
+          hipLaunchKernelGGL(k_pcg_vec_mg<4>, vg, dim3(kBlock), 0, ss, d, (const float*)r1, p,
+                             (const uint16_t*)c->m16, c->mg_fine, c->mg_geom[1], mg_final(c, 1), kMgOmegaFine,
+                             (const DevState*)c->st);
+        } else {
+          hipLaunchKernelGGL(k_fin_init_pcg, dim3(1), dim3(kFinBlock), 0, ss, c->st, c->partials, (int)(vg.x * vg.y),
+                             itol * itol);
+        }
         PN_HIP(hipGetLastError());
         for (;;) {
           PN_HIP(hipGraphLaunch(*gexec, ss));
@@ -1338,7 +1535,7 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
     info->t_ms[PN_PHASE_RESIDUAL] = t_res;
     info->t_ms[PN_PHASE_KRYLOV] = t_kry;
     info->t_ms[PN_PHASE_LEARNED] = t_net;
-    const SolveBytes sb = schur ? schur_bytes(c) : solve_bytes(c, sizeof(T) == 8, cg, eq);
+    const SolveBytes sb = schur ? schur_bytes(c, mg) : solve_bytes(c, sizeof(T) == 8, cg, eq);
     info->bytes = sb.per_iter * info->inner_iters + sb.per_start * starts + sb.per_resid * outer;
     info->achieved_gbs = (t_res + t_kry) > 0.0 ? info->bytes / ((t_res + t_kry) * 1e6) : 0.0;
   }
@@ -1359,9 +1556,12 @@ extern "C" pn_status pn_solve(pn_ctx* c, const float* rhs, double* x, double tol
   if (o.precision != PN_FP32_IR && o.precision != PN_FP64) return fail(c, PN_ERR_ARG, "unknown precision");
   if (o.learned < PN_LEARNED_OFF || o.learned > PN_LEARNED_GUESS_CORRECT)
     return fail(c, PN_ERR_ARG, "unknown learned mode");
-  if (o.variant < PN_VARIANT_AUTO || o.variant > PN_VARIANT_SCHUR) return fail(c, PN_ERR_ARG, "unknown variant");
+  if (o.variant < PN_VARIANT_AUTO || o.variant > PN_VARIANT_SCHUR_MG) return fail(c, PN_ERR_ARG, "unknown variant");
   if (o.variant == PN_VARIANT_SCHUR && (!schur_ok(c) || o.precision != PN_FP32_IR))
     return fail(c, PN_ERR_ARG, "the even-parity Schur variant needs FP32_IR, no Neumann axis and positive extinction");
+  if (o.variant == PN_VARIANT_SCHUR_MG && (!mg_ok(c) || c->use_lds || o.precision != PN_FP32_IR))
+    return fail(c, PN_ERR_ARG, "the multigrid even-parity variant needs FP32_IR, the register-window stencil, the "
+                               "vacuum boundary on every axis and positive extinction");
   if (o.variant == PN_VARIANT_CG_EQ && (c->use_lds || o.precision != PN_FP32_IR))
     return fail(c, PN_ERR_ARG, "the equilibrated CG variant needs FP32_IR and the register-window stencil");
   if (info) std::memset(info, 0, sizeof(*info));

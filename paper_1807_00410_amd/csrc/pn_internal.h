@@ -10,6 +10,7 @@
 #include "../../include/pn.h"
 #include "../../include/pn_nn.h"
 #include "pn_launch.h"
+#include "pn_mg.h"
 
 namespace pn {  // instantiated in pn_order_N.hip
 extern template hipError_t launch_order<1>(int, bool, bool, const StencilArgs&, hipStream_t);
@@ -92,6 +93,20 @@ struct pn_ctx {
   int giters_schur = 0;
   EvenSlots even{};                   // even-band coefficient arrays of the padded vectors
   hipGraphExec_t gexec_cg = nullptr;  // captured CG-on-normal-equations iterations
+  // multigrid preconditioner of the even-parity PCG (levels 1..mg_levels,
+  // allocated on first use; geometry [0] = the class extents of the even slots)
+  int mg_levels = 0;
+  MgFine mg_fine{};
+  MgGeom mg_geom[kMgMaxLevels] = {};
+  MgTerms* mg_terms = nullptr;
+  float4* mg_op[kMgMaxLevels] = {};
+  float* mg_r[kMgMaxLevels] = {};
+  float* mg_z[kMgMaxLevels] = {};
+  float* mg_zt[kMgMaxLevels] = {};
+  double* mg_partials = nullptr;
+  int mg_npart = 0;  // block partial pairs of <P^T r, V(P^T r)>
+  hipGraphExec_t gexec_mg = nullptr;
+  int giters_mg = 0;
   int giters_cg = 0;
   int gcg_eq = 0;                     // gexec_cg holds the row-equilibrated form
   // learned initial guess / correction (pn_attach_net)
@@ -143,8 +158,11 @@ inline SolveBytes solve_bytes(const pn_ctx* c, bool fp64, bool cg, bool eq) {
 
 // Even-parity PCG: per iteration the odd rows (read the even part of p,
 // write the odd part), the even rows (read all of p, r and m in bfloat16,
-// write r), x/p (x, p, r, m; write x, p); the medium per stencil pass.
-inline SolveBytes schur_bytes(const pn_ctx* c) {
+// write r), x/p (x, p, r, m; write x, p); the medium per stencil pass.  With
+// the multigrid preconditioner also: the restriction (read r), the level-1
+// correction read by the x/p pass, and per coarse level the V-cycle's two
+// passes (operator 16 B, r, z, z' per point) and the coarsest sweeps.
+inline SolveBytes schur_bytes(const pn_ctx* c, bool mg = false) {
   double ne = 0.0;
   for (int j = 0; j < c->even.nk; ++j) {
     const int k = c->even.k[j];
@@ -153,6 +171,13 @@ inline SolveBytes schur_bytes(const pn_ctx* c) {
   const double n = (double)c->n, no = n - ne, cells = (double)c->nx * c->ny * c->nz;
   SolveBytes b;
   b.per_iter = 4.0 * (ne + no) + (4.0 * n + 10.0 * ne) + 22.0 * ne + 16.0 * cells;
+  if (mg && c->mg_levels > 0) {
+    b.per_iter += 4.0 * ne + 4.0 * (double)c->mg_geom[1].off[c->mg_geom[1].nk];
+    for (int L = 1; L <= c->mg_levels; ++L) {
+      const double nl = (double)c->mg_geom[L].off[c->mg_geom[L].nk];
+      b.per_iter += L < c->mg_levels ? nl * (16.0 + 4.0 + 4.0) + nl * (16.0 + 4.0 + 4.0 + 4.0) : nl * 24.0 * 16.0;
+    }
+  }
   b.per_start = 3.0 * n * 4.0 + 4.0 * ne * 4.0 + 16.0 * cells + (ne + n) * 4.0 + 12.0 * n;
   b.per_resid = 16.0 * n + 8.0 * cells;
   return b;

@@ -48,6 +48,7 @@ struct DevState {
   double bb2;     // ||Q||^2
   double nonfinite;
   double itol2;   // batch: squared relative tolerance of the next inner solve
+  double rzf;     // multigrid PCG: <r, M r> of the current residual (its Jacobi part)
   int iters;      // Krylov iterations so far (all inner solves)
   int max_iters;
   int stop;       // set when the iteration must end after this step's update

@@ -1,0 +1,374 @@
+// Kernels of the multigrid preconditioner (structures and design notes in
+// pn_mg.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pn_kernels.h"
+#include "pn_mg.h"
+
+namespace pn {
+
+__device__ __forceinline__ long long mg_at(const MgGeom& g, int s, int x, int y, int z) {
+  return g.off[s] + ((long long)z * g.ext[s][1] + y) * g.ext[s][0] + x;
+}
+
+__device__ __forceinline__ void mg_xyz(const MgGeom& g, int s, long long i, int& x, int& y, int& z) {
+  const int ex = g.ext[s][0], ey = g.ext[s][1];
+  x = (int)(i % ex);
+  const long long t = i / ex;
+  y = (int)(t % ey);
+  z = (int)(t / ey);
+}
+
+// Fine face weight of slot s between the padded point pidx and pidx + e_d.
+__device__ __forceinline__ double mg_fine_w(const MgFine& f, const MgTerms* __restrict__ t,
+                                            const float* __restrict__ invdo, int s, long long pidx, int d) {
+  const long long stride = d == 0 ? 1 : (d == 1 ? (long long)f.PX : (long long)f.PX * f.PY);
+  const long long q = pidx + (1 - f.cls[s][d]) * stride;  // the odd point between the two
+  double w = 0.0;
+  for (int i = 0; i < t->n[s][d]; ++i) w += (double)t->c2[s][d][i] * (double)invdo[(long long)t->j[s][d][i] * f.cs + q];
+  return w;
+}
+
+// Level-1 operator {diag, w_x, w_y, w_z} (w_d: weight to the + neighbour):
+// sums over the aggregate's children of the fine operator, internal faces
+// cancelling.  m32: 1 / diag(S) in the even slots; invdo: 1 / d_o in the odd
+// slots.  Grid: (blocks, slots).
+static __global__ void __launch_bounds__(kBlock) k_mg_setup1(const MgFine f, const MgGeom g1,
+                                                             const MgTerms* __restrict__ t,
+                                                             const float* __restrict__ m32,
+                                                             const float* __restrict__ invdo, double invh2,
+                                                             float4* __restrict__ op) {
+  const int s = blockIdx.y;
+  const long long n = (long long)g1.ext[s][0] * g1.ext[s][1] * g1.ext[s][2];
+  const int fe[3] = {f.ext[s][0], f.ext[s][1], f.ext[s][2]};
+  const long long stride[3] = {1, (long long)f.PX, (long long)f.PX * f.PY};
+  const long long base = (long long)f.k[s] * f.cs;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    int X[3];
+    mg_xyz(g1, s, i, X[0], X[1], X[2]);
+    double diag = 0.0, wp[3] = {0.0, 0.0, 0.0}, wm[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < 8; ++c) {
+      const int cc[3] = {c & 1, (c >> 1) & 1, c >> 2};
+      const int xc[3] = {2 * X[0] + cc[0], 2 * X[1] + cc[1], 2 * X[2] + cc[2]};
+      if (xc[0] >= fe[0] || xc[1] >= fe[1] || xc[2] >= fe[2]) continue;
+      const long long pidx = ((long long)(xc[2] + 1) * f.PY + (xc[1] + 1)) * f.PX + (xc[0] + 1);
+      double all = 0.0, kept = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        const double wpl = invh2 * mg_fine_w(f, t, invdo, s, pidx, d);
+        const double wmi = invh2 * mg_fine_w(f, t, invdo, s, pidx - stride[d], d);
+        all += wpl + wmi;
+        const bool has_p = xc[d] + 1 < fe[d];
+        if (!(cc[d] == 0 && has_p)) kept += wpl;  // + face not internal
+        if (cc[d] == 0) kept += wmi;              // - face not internal (cc = 1: the sibling 2X)
+        if (cc[d] == 1 && has_p) wp[d] += wpl;
+        if (cc[d] == 0 && xc[d] >= 1) wm[d] += wmi;
+      }
+      const double de = 1.0 / (double)m32[base + pidx] - all;  // d_e(x)
+      diag += fmax(de, 0.0) + kept;
+    }
+    const double off = wp[0] + wp[1] + wp[2] + wm[0] + wm[1] + wm[2];
+    diag = fmax(diag, (1.0 + 1e-6) * off);
+    op[g1.off[s] + i] = make_float4((float)diag, (float)wp[0], (float)wp[1], (float)wp[2]);
+  }
+}
+
+// Galerkin coarsening of an explicit level (aggregates of 2 x 2 x 2).
+static __global__ void __launch_bounds__(kBlock) k_mg_coarsen(const MgGeom gf, const MgGeom gc,
+                                                              const float4* __restrict__ opf,
+                                                              float4* __restrict__ opc) {
+  const int s = blockIdx.y;
+  const long long n = (long long)gc.ext[s][0] * gc.ext[s][1] * gc.ext[s][2];
+  const int fe[3] = {gf.ext[s][0], gf.ext[s][1], gf.ext[s][2]};
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    int X[3];
+    mg_xyz(gc, s, i, X[0], X[1], X[2]);
+    double diag = 0.0, wp[3] = {0.0, 0.0, 0.0}, wm[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < 8; ++c) {
+      const int cc[3] = {c & 1, (c >> 1) & 1, c >> 2};
+      const int xc[3] = {2 * X[0] + cc[0], 2 * X[1] + cc[1], 2 * X[2] + cc[2]};
+      if (xc[0] >= fe[0] || xc[1] >= fe[1] || xc[2] >= fe[2]) continue;
+      const float4 o = opf[mg_at(gf, s, xc[0], xc[1], xc[2])];
+      const double w[3] = {o.y, o.z, o.w};
+      diag += (double)o.x;
+      for (int d = 0; d < 3; ++d) {
+        const bool has_p = xc[d] + 1 < fe[d];
+        if (cc[d] == 0 && has_p) diag -= 2.0 * w[d];  // internal pair
+        if (cc[d] == 1 && has_p) wp[d] += w[d];
+        if (cc[d] == 0 && xc[d] >= 1) {
+          int xm[3] = {xc[0], xc[1], xc[2]};
+          xm[d] -= 1;
+          const float4 om = opf[mg_at(gf, s, xm[0], xm[1], xm[2])];
+          wm[d] += d == 0 ? (double)om.y : (d == 1 ? (double)om.z : (double)om.w);
+        }
+      }
+    }
+    const double off = wp[0] + wp[1] + wp[2] + wm[0] + wm[1] + wm[2];
+    diag = fmax(diag, (1.0 + 1e-6) * off);
+    opc[gc.off[s] + i] = make_float4((float)diag, (float)wp[0], (float)wp[1], (float)wp[2]);
+  }
+}
+
+// r1 = P^T r: the fine residual (even slots of the padded r) summed over each
+// aggregate.
+static __global__ void __launch_bounds__(kBlock) k_mg_restrict0(const MgFine f, const MgGeom g1,
+                                                                const float* __restrict__ r, float* __restrict__ r1,
+                                                                const DevState* __restrict__ st) {
+  if (st->stop) return;
+  const int s = blockIdx.y;
+  const long long n = (long long)g1.ext[s][0] * g1.ext[s][1] * g1.ext[s][2];
+  const int fe[3] = {f.ext[s][0], f.ext[s][1], f.ext[s][2]};
+  const float* rs = r + (long long)f.k[s] * f.cs;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    int X, Y, Z;
+    mg_xyz(g1, s, i, X, Y, Z);
+    float acc = 0.f;
+    for (int c = 0; c < 8; ++c) {
+      const int x = 2 * X + (c & 1), y = 2 * Y + ((c >> 1) & 1), z = 2 * Z + (c >> 2);
+      if (x >= fe[0] || y >= fe[1] || z >= fe[2]) continue;
+      acc += rs[((long long)(z + 1) * f.PY + (y + 1)) * f.PX + (x + 1)];
+    }
+    r1[g1.off[s] + i] = acc;
+  }
+}
+
+// (A z)(x) - diag(x) z(x) for the explicit operator, z given pointwise by ZF.
+template <typename ZF>
+__device__ __forceinline__ float mg_offdiag(const MgGeom& g, int s, const float4* __restrict__ op, const float4& o,
+                                            int x, int y, int z, ZF zf) {
+  const int e[3] = {g.ext[s][0], g.ext[s][1], g.ext[s][2]};
+  float acc = 0.f;
+  if (x + 1 < e[0]) acc -= o.y * zf(x + 1, y, z);
+  if (y + 1 < e[1]) acc -= o.z * zf(x, y + 1, z);
+  if (z + 1 < e[2]) acc -= o.w * zf(x, y, z + 1);
+  if (x >= 1) acc -= op[mg_at(g, s, x - 1, y, z)].y * zf(x - 1, y, z);
+  if (y >= 1) acc -= op[mg_at(g, s, x, y - 1, z)].z * zf(x, y - 1, z);
+  if (z >= 1) acc -= op[mg_at(g, s, x, y, z - 1)].w * zf(x, y, z - 1);
+  return acc;
+}
+
+// Down the V-cycle at level L: z_L = omega r_L / diag (one damped Jacobi
+// sweep from zero), r_{L+1} = P^T (r_L - A_L z_L).  One thread per point of
+// level L + 1.
+static __global__ void __launch_bounds__(kBlock) k_mg_down(const MgGeom gf, const MgGeom gc,
+                                                           const float4* __restrict__ op, const float* __restrict__ r,
+                                                           float* __restrict__ zo, float* __restrict__ rc, float omega,
+                                                           const DevState* __restrict__ st) {
+  if (st->stop) return;
+  const int s = blockIdx.y;
+  const long long n = (long long)gc.ext[s][0] * gc.ext[s][1] * gc.ext[s][2];
+  const int fe[3] = {gf.ext[s][0], gf.ext[s][1], gf.ext[s][2]};
+  auto zf = [&](int x, int y, int z) {
+    const long long j = mg_at(gf, s, x, y, z);
+    return omega * r[j] / op[j].x;
+  };
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    int X, Y, Z;
+    mg_xyz(gc, s, i, X, Y, Z);
+    float acc = 0.f;
+    for (int c = 0; c < 8; ++c) {
+      const int x = 2 * X + (c & 1), y = 2 * Y + ((c >> 1) & 1), z = 2 * Z + (c >> 2);
+      if (x >= fe[0] || y >= fe[1] || z >= fe[2]) continue;
+      const long long j = mg_at(gf, s, x, y, z);
+      const float4 o = op[j];
+      const float rv = r[j];
+      const float zv = omega * rv / o.x;
+      zo[j] = zv;
+      acc += rv - (o.x * zv + mg_offdiag(gf, s, op, o, x, y, z, zf));
+    }
+    rc[gc.off[s] + i] = acc;
+  }
+}
+
+// Up the V-cycle at level L: z' = z_L + P z_{L+1}, then one damped Jacobi
+// sweep z'' = z' + omega (r_L - A_L z') / diag into zo.  With `partials`,
+// also the block sums of <r_L, z''> (level 1: the coarse part of <r, B r>).
+static __global__ void __launch_bounds__(kBlock) k_mg_up(const MgGeom gf, const MgGeom gc,
+                                                         const float4* __restrict__ op, const float* __restrict__ r,
+                                                         const float* __restrict__ zl, const float* __restrict__ zc,
+                                                         float* __restrict__ zo, float omega,
+                                                         double* __restrict__ partials,
+                                                         const DevState* __restrict__ st) {
+  if (st->stop) return;
+  const int s = blockIdx.y;
+  const long long n = (long long)gf.ext[s][0] * gf.ext[s][1] * gf.ext[s][2];
+  auto zf = [&](int x, int y, int z) {
+    return zl[mg_at(gf, s, x, y, z)] + zc[mg_at(gc, s, x >> 1, y >> 1, z >> 1)];
+  };
+  double s0 = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+    int x, y, z;
+    mg_xyz(gf, s, i, x, y, z);
+    const long long j = gf.off[s] + i;
+    const float4 o = op[j];
+    const float zp = zf(x, y, z);
+    const float rv = r[j];
+    const float out = zp + omega * (rv - (o.x * zp + mg_offdiag(gf, s, op, o, x, y, z, zf))) / o.x;
+    zo[j] = out;
+    s0 += (double)(rv * out);
+  }
+  if (partials) {
+    double unused = 0.0;
+    block_sum2(s0, unused);
+    if (threadIdx.x == 0) {
+      const int b = blockIdx.y * gridDim.x + blockIdx.x;
+      partials[2 * b] = s0;
+      partials[2 * b + 1] = 0.0;
+    }
+  }
+}
+
+// Coarsest level: `sweeps` damped Jacobi sweeps from zero, one block (the
+// level holds a few thousand points); the result ends in za.  With
+// `partials`, partials[0] = <r, z> (the coarsest level is level 1).
+static __global__ void __launch_bounds__(kFinBlock) k_mg_coarsest(const MgGeom g, const float4* __restrict__ op,
+                                                                  const float* __restrict__ r, float* __restrict__ za,
+                                                                  float* __restrict__ zb, int sweeps, float omega,
+                                                                  double* __restrict__ partials,
+                                                                  const DevState* __restrict__ st) {
+  __shared__ double red[kFinBlock / 64];
+  if (st->stop) return;
+  const long long n = g.off[g.nk];
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) za[i] = omega * r[i] / op[i].x;
+  __syncthreads();
+  float* cur = za;
+  float* nxt = zb;
+  for (int t = 1; t < sweeps; ++t) {
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+      int s = 0;
+      while (s + 1 < g.nk && i >= g.off[s + 1]) ++s;
+      int x, y, z;
+      mg_xyz(g, s, i - g.off[s], x, y, z);
+      const float4 o = op[i];
+      auto zf = [&](int xx, int yy, int zz) { return cur[mg_at(g, s, xx, yy, zz)]; };
+      nxt[i] = cur[i] + omega * (r[i] - (o.x * cur[i] + mg_offdiag(g, s, op, o, x, y, z, zf))) / o.x;
+    }
+    __syncthreads();
+    float* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  if (cur != za) {
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) za[i] = cur[i];
+    __syncthreads();
+  }
+  if (partials) {
+    double s0 = 0.0, unused = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) s0 += (double)(r[i] * za[i]);
+    s0 = wave_sum(s0);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += red[w];
+      partials[0] = a;
+      partials[1] = unused;
+    }
+  }
+}
+
+// After the r update: <r, M r> kept for the coarse part, <r, r> tested.
+// INIT: the start of an inner solve (as fin_init_pcg, gamma formed later).
+template <bool INIT>
+__global__ void __launch_bounds__(kFinBlock) k_fin_rz_mg(DevState* st, const double* partials, int n,
+                                                         double inner_tol2) {
+  if (!INIT && (st->done || st->stop)) return;
+  double rz, rr;
+  grid_sum2(partials, n, rz, rr);
+  if (threadIdx.x == 0) {
+    st->rzf = rz;
+    st->rr = rr;
+    if (INIT) {
+      st->rr0 = st->rtrue2;
+      st->tol2 = inner_tol2 * st->rtrue2;
+      st->stop = (rz > 0.0 && finite_d(rz) && rr > st->tol2) ? 0 : 1;
+      st->done = 0;
+      st->breakdown = 0;
+      st->alpha = 0.0;
+      st->beta = 0.0;
+      st->gamma = 0.0;
+    } else {
+      st->iters += 1;
+      if (!finite_d(rr) || !finite_d(rz)) { st->breakdown = 1; st->stop = 1; st->nonfinite = 1.0; }
+      if (rr <= st->tol2 || st->iters >= st->max_iters || !(rz > 0.0)) st->stop = 1;
+    }
+  }
+}
+
+// gamma' = <r, B r> = omega_f <r, M r> + <P^T r, V(P^T r)>, beta = gamma' / gamma.
+template <bool INIT>
+__global__ void __launch_bounds__(kFinBlock) k_fin_beta_mg(DevState* st, const double* partials, int n,
+                                                           double omega_f) {
+  if (st->done || st->stop) return;
+  double cz, unused;
+  grid_sum2(partials, n, cz, unused);
+  if (threadIdx.x == 0) {
+    const double gnew = omega_f * st->rzf + cz;
+    if (!(gnew > 0.0) || !finite_d(gnew)) {
+      st->breakdown = 1;
+      st->stop = 1;
+      st->beta = 0.0;
+    } else {
+      st->beta = INIT ? 0.0 : gnew / st->gamma;
+      st->gamma = gnew;
+    }
+  }
+}
+
+// OP 2: x += alpha p, p = B r + beta p;  OP 4 (start): p = B r, with
+// B r = omega_f m r + z1 at the point's aggregate (zero outside the class
+// extent, where r and p stay zero).
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_pcg_vec_mg(float* __restrict__ x, const float* __restrict__ r,
+                                                       float* __restrict__ p, const uint16_t* __restrict__ m,
+                                                       const MgFine f, const MgGeom g1, const float* __restrict__ z1,
+                                                       float omega_f, const DevState* __restrict__ st) {
+  if (OP == 2 && st->done) return;
+  const int s = blockIdx.y;
+  const long long base = (long long)f.k[s] * f.cs;
+  const long long n4 = f.cs >> 2;
+  const long long stride = (long long)gridDim.x * kBlock;
+  const float al = OP == 2 ? float(st->alpha) : 0.f, be = OP == 2 ? float(st->beta) : 0.f;
+  const int fx = f.ext[s][0], fy = f.ext[s][1], fz = f.ext[s][2];
+  const int ex1 = g1.ext[s][0], ey1 = g1.ext[s][1];
+  const float* zs = z1 + g1.off[s];
+  float4* x4 = reinterpret_cast<float4*>(x + base);
+  const float4* r4 = reinterpret_cast<const float4*>(r + base);
+  float4* p4 = reinterpret_cast<float4*>(p + base);
+  const uint2* m4 = reinterpret_cast<const uint2*>(m + base);
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride) {
+    const float4 rv = ld_nt(r4 + i);
+    const float4 mv = ld_bf4(m4 + i);
+    // lattice coordinates of the four elements
+    long long j = 4 * i;
+    int xp = (int)(j % f.PX);
+    long long t = j / f.PX;
+    int yp = (int)(t % f.PY), zp = (int)(t / f.PY);
+    float cz[4];
+    for (int e = 0; e < 4; ++e) {
+      const int xx = xp - 1, yy = yp - 1, zz = zp - 1;
+      cz[e] = (xx >= 0 && xx < fx && yy >= 0 && yy < fy && zz >= 0 && zz < fz)
+                  ? zs[((long long)(zz >> 1) * ey1 + (yy >> 1)) * ex1 + (xx >> 1)]
+                  : 0.f;
+      if (++xp == f.PX) { xp = 0; if (++yp == f.PY) { yp = 0; ++zp; } }
+    }
+    float4 z;
+    z.x = __fmaf_rn(omega_f * mv.x, rv.x, cz[0]);
+    z.y = __fmaf_rn(omega_f * mv.y, rv.y, cz[1]);
+    z.z = __fmaf_rn(omega_f * mv.z, rv.z, cz[2]);
+    z.w = __fmaf_rn(omega_f * mv.w, rv.w, cz[3]);
+    if constexpr (OP == 2) {
+      float4 pv = ld_nt(p4 + i), xv = ld_nt(x4 + i);
+      xv.x = __fmaf_rn(al, pv.x, xv.x); xv.y = __fmaf_rn(al, pv.y, xv.y);
+      xv.z = __fmaf_rn(al, pv.z, xv.z); xv.w = __fmaf_rn(al, pv.w, xv.w);
+      pv.x = __fmaf_rn(be, pv.x, z.x); pv.y = __fmaf_rn(be, pv.y, z.y);
+      pv.z = __fmaf_rn(be, pv.z, z.z); pv.w = __fmaf_rn(be, pv.w, z.w);
+      st_nt(x4 + i, xv);
+      st_nt(p4 + i, pv);
+    } else {
+      st_nt(p4 + i, z);
+    }
+  }
+}
+
+}  // namespace pn

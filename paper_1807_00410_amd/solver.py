@@ -252,7 +252,7 @@ def _opts(lib, precision, max_iter, max_refine, inner_tol, use_guess, graph_iter
     opts.inner_tol = float(inner_tol)
     opts.use_guess = int(bool(use_guess))
     opts.graph_iters = int(graph_iters)
-    opts.variant = {"auto": 0, "cgls": 1, "cg": 2, "cg_eq": 3, "schur": 4}[variant]
+    opts.variant = {"auto": 0, "cgls": 1, "cg": 2, "cg_eq": 3, "schur": 4, "schur_mg": 5}[variant]
     return opts
 
 
