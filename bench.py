@@ -392,6 +392,27 @@ def profile_kernels(args):
     s.close()
 
 
+def profile_solve(args):
+    """Profiling mode for rocprofv3 (--profile-solve): the headline workload
+    (P5 nebula) solved by the default solver once untimed, then
+    `--profile-iters` times, nothing else -- the kernel trace of a real solve
+    (every kernel of the Krylov loop and the preconditioner, with their
+    per-launch durations)."""
+    import torch
+    from synth import config_p5_nebula
+    from paper_1807_00410_amd.solver import Solver
+    m = config_p5_nebula(n=args.n, order=args.order, g=args.g)
+    s = Solver(m.order, m.dims, torch.as_tensor(m.sigma_t).cuda(), torch.as_tensor(m.albedo).cuda(),
+               g=m.g, sigma_t_min=m.sigma_t_min)
+    s.set_zchunk(args.profile_zchunk)
+    rhs = s.rhs_from_q00(torch.as_tensor(m.q00[0]).cuda())
+    for i in range(1 + args.profile_iters):
+        x, info = s.solve(rhs, tol=args.tol, inner_tol=args.inner_tol)
+        print("solve %d: %.4f s, %d iterations, %d refinement steps, rel %.3g" % (
+            i, info["seconds"], info["inner_iters"], info["outer_iters"], info["rel_residual"]), flush=True)
+    s.close()
+
+
 def accuracy_check(args):
     """--accuracy: the P5 128^3 nebula (g = 0 and 0.5) solved to 1e-8 by the
     default inner solver, the equilibrated normal equations and FP64 CGLS,
@@ -455,6 +476,9 @@ def main():
                          "apply_eq, supd, update) "
                          "run in their in-loop form for rocprofv3, then the counter-calibration copies")
     ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="solve the P5 nebula 1 + --profile-iters times with the default solver, nothing else "
+                         "(the kernel trace of a real solve for rocprofv3)")
     ap.add_argument("--accuracy", action="store_true",
                     help="compare the P5 128^3 solutions with the oracle's reference solutions in refdata/")
     ap.add_argument("--profile-zchunk", type=int, default=2)
@@ -465,6 +489,9 @@ def main():
         sys.exit(2)
     if args.profile_kernels:
         profile_kernels(args)
+        return
+    if args.profile_solve:
+        profile_solve(args)
         return
     if args.accuracy:
         accuracy_check(args)

@@ -994,8 +994,9 @@ static pn_status mg_alloc(pn_ctx* c) {
       b.off[s + 1] = b.off[s] + mg_points(b, s);
     }
     ++levels;
-    if (mx <= kMgCoarsest || levels + 1 >= kMgMaxLevels) break;
+    if ((mx <= kMgCoarsest && b.off[b.nk] <= kMgCoarseMax) || levels + 1 >= kMgMaxLevels) break;
   }
+  if (g[levels].off[g[levels].nk] > kMgCoarseMax) return fail(c, PN_ERR_ARG, "multigrid: coarsest level too large");
   // squared couplings of every even row per axis
   MgTerms t;
   std::memset(&t, 0, sizeof(t));
@@ -1044,6 +1045,18 @@ static pn_status mg_setup_ops(pn_ctx* c, const float* m32, const float* invdo, h
   return PN_OK;
 }
 
+// Grid of the tiled aggregation kernels over level f (coarse level c): tiles
+// of the largest (x, y) extent, coarse z planes of the deepest slot, slots.
+static dim3 mg_tiles(const MgGeom& f, const MgGeom& c) {
+  int tx = 0, ty = 0, zc = 0;
+  for (int s = 0; s < f.nk; ++s) {
+    tx = std::max(tx, (f.ext[s][0] + kMgTile - 1) / kMgTile);
+    ty = std::max(ty, (f.ext[s][1] + kMgTile - 1) / kMgTile);
+    zc = std::max(zc, c.ext[s][2]);
+  }
+  return dim3(tx * ty, zc, f.nk);
+}
+
 static const float* mg_final(const pn_ctx* c, int L) { return L == c->mg_levels ? c->mg_z[L] : c->mg_zt[L]; }
 
 // One V-cycle on P^T r (fine r: the even slots of the padded r); the level-1
@@ -1053,12 +1066,13 @@ static hipError_t mg_vcycle(pn_ctx* c, const float* r, hipStream_t st) {
   const int Lc = c->mg_levels;
   const DevState* ds = c->st;
   hipLaunchKernelGGL(k_mg_restrict0, dim3(mg_blocks(g[1]), g[1].nk), dim3(kBlock), 0, st, c->mg_fine, g[1], r,
-                     c->mg_r[1], ds);
+                     (const float4*)c->mg_op[1], c->mg_r[1], c->mg_z[1], kMgOmega, ds);
   for (int L = 1; L < Lc; ++L)
-    hipLaunchKernelGGL(k_mg_down, dim3(mg_blocks(g[L + 1]), g[L + 1].nk), dim3(kBlock), 0, st, g[L], g[L + 1],
-                       (const float4*)c->mg_op[L], (const float*)c->mg_r[L], c->mg_z[L], c->mg_r[L + 1], kMgOmega, ds);
+    hipLaunchKernelGGL(k_mg_down, mg_tiles(g[L], g[L + 1]), dim3(kBlock), 0, st, g[L], g[L + 1],
+                       (const float4*)c->mg_op[L], (const float*)c->mg_r[L], (const float*)c->mg_z[L],
+                       (const float4*)c->mg_op[L + 1], c->mg_r[L + 1], c->mg_z[L + 1], kMgOmega, ds);
   hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(kFinBlock), 0, st, g[Lc], (const float4*)c->mg_op[Lc],
-                     (const float*)c->mg_r[Lc], c->mg_z[Lc], c->mg_zt[Lc], kMgSweeps, kMgOmega,
+                     (const float*)c->mg_r[Lc], c->mg_z[Lc], kMgSweeps, kMgOmega,
                      Lc == 1 ? c->mg_partials : (double*)nullptr, ds);
   for (int L = Lc - 1; L >= 1; --L)
     hipLaunchKernelGGL(k_mg_up, dim3(mg_blocks(g[L]), g[L].nk), dim3(kBlock), 0, st, g[L], g[L + 1],

@@ -8,17 +8,24 @@
 
 namespace pn {
 
+// A level holds at most a few million points per slot: 32-bit local indices.
 __device__ __forceinline__ long long mg_at(const MgGeom& g, int s, int x, int y, int z) {
-  return g.off[s] + ((long long)z * g.ext[s][1] + y) * g.ext[s][0] + x;
+  return g.off[s] + (long long)((z * g.ext[s][1] + y) * g.ext[s][0] + x);
 }
 
-__device__ __forceinline__ void mg_xyz(const MgGeom& g, int s, long long i, int& x, int& y, int& z) {
-  const int ex = g.ext[s][0], ey = g.ext[s][1];
-  x = (int)(i % ex);
-  const long long t = i / ex;
-  y = (int)(t % ey);
+__device__ __forceinline__ void mg_xyz(const MgGeom& g, int s, int i, int& x, int& y, int& z) {
+  const unsigned ex = (unsigned)g.ext[s][0], ey = (unsigned)g.ext[s][1];
+  const unsigned t = (unsigned)i / ex;
+  x = i - (int)(t * ex);
   z = (int)(t / ey);
+  y = (int)t - z * (int)ey;
 }
+
+__device__ __forceinline__ int mg_points(const MgGeom& g, int s) { return g.ext[s][0] * g.ext[s][1] * g.ext[s][2]; }
+
+// Every Jacobi step uses this reciprocal of the diagonal (the same fixed
+// scaling in every sweep, so the V-cycle stays symmetric).
+__device__ __forceinline__ float mg_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
 
 // Fine face weight of slot s between the padded point pidx and pidx + e_d.
 __device__ __forceinline__ double mg_fine_w(const MgFine& f, const MgTerms* __restrict__ t,
@@ -40,11 +47,11 @@ static __global__ void __launch_bounds__(kBlock) k_mg_setup1(const MgFine f, con
                                                              const float* __restrict__ invdo, double invh2,
                                                              float4* __restrict__ op) {
   const int s = blockIdx.y;
-  const long long n = (long long)g1.ext[s][0] * g1.ext[s][1] * g1.ext[s][2];
+  const int n = mg_points(g1, s);
   const int fe[3] = {f.ext[s][0], f.ext[s][1], f.ext[s][2]};
   const long long stride[3] = {1, (long long)f.PX, (long long)f.PX * f.PY};
   const long long base = (long long)f.k[s] * f.cs;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     int X[3];
     mg_xyz(g1, s, i, X[0], X[1], X[2]);
     double diag = 0.0, wp[3] = {0.0, 0.0, 0.0}, wm[3] = {0.0, 0.0, 0.0};
@@ -78,9 +85,9 @@ static __global__ void __launch_bounds__(kBlock) k_mg_coarsen(const MgGeom gf, c
                                                               const float4* __restrict__ opf,
                                                               float4* __restrict__ opc) {
   const int s = blockIdx.y;
-  const long long n = (long long)gc.ext[s][0] * gc.ext[s][1] * gc.ext[s][2];
+  const int n = mg_points(gc, s);
   const int fe[3] = {gf.ext[s][0], gf.ext[s][1], gf.ext[s][2]};
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     int X[3];
     mg_xyz(gc, s, i, X[0], X[1], X[2]);
     double diag = 0.0, wp[3] = {0.0, 0.0, 0.0}, wm[3] = {0.0, 0.0, 0.0};
@@ -110,25 +117,33 @@ static __global__ void __launch_bounds__(kBlock) k_mg_coarsen(const MgGeom gf, c
 }
 
 // r1 = P^T r: the fine residual (even slots of the padded r) summed over each
-// aggregate.
+// aggregate, and z1 = omega r1 / diag (the first damped Jacobi sweep of the
+// level-1 V-cycle, from zero).  One thread per aggregate: a wave reads 128
+// consecutive fine x of each of its four (y, z) rows (tiles of 16 x 16 fine
+// columns read this layout in 64-byte pieces and were measured 2x slower).
 static __global__ void __launch_bounds__(kBlock) k_mg_restrict0(const MgFine f, const MgGeom g1,
-                                                                const float* __restrict__ r, float* __restrict__ r1,
-                                                                const DevState* __restrict__ st) {
+                                                                const float* __restrict__ r,
+                                                                const float4* __restrict__ op1,
+                                                                float* __restrict__ r1, float* __restrict__ z1,
+                                                                float omega, const DevState* __restrict__ st) {
   if (st->stop) return;
   const int s = blockIdx.y;
-  const long long n = (long long)g1.ext[s][0] * g1.ext[s][1] * g1.ext[s][2];
+  const int n = mg_points(g1, s);
   const int fe[3] = {f.ext[s][0], f.ext[s][1], f.ext[s][2]};
   const float* rs = r + (long long)f.k[s] * f.cs;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+  const int PX = f.PX, PY = f.PY;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     int X, Y, Z;
     mg_xyz(g1, s, i, X, Y, Z);
     float acc = 0.f;
     for (int c = 0; c < 8; ++c) {
       const int x = 2 * X + (c & 1), y = 2 * Y + ((c >> 1) & 1), z = 2 * Z + (c >> 2);
       if (x >= fe[0] || y >= fe[1] || z >= fe[2]) continue;
-      acc += rs[((long long)(z + 1) * f.PY + (y + 1)) * f.PX + (x + 1)];
+      acc += rs[((z + 1) * PY + (y + 1)) * PX + (x + 1)];
     }
-    r1[g1.off[s] + i] = acc;
+    const long long j = g1.off[s] + i;
+    r1[j] = acc;
+    z1[j] = omega * acc * mg_rcp(op1[j].x);
   }
 }
 
@@ -147,36 +162,49 @@ __device__ __forceinline__ float mg_offdiag(const MgGeom& g, int s, const float4
   return acc;
 }
 
-// Down the V-cycle at level L: z_L = omega r_L / diag (one damped Jacobi
-// sweep from zero), r_{L+1} = P^T (r_L - A_L z_L).  One thread per point of
-// level L + 1.
+// Tiles of the aggregating down pass: 16 x 16 points (x, y) per block of 256
+// threads, each thread two z planes (one coarse plane); a wave holds four
+// rows of 16, so the x partner of a lane is lane ^ 1 and the y partner
+// lane ^ 16, and the 2 x 2 x 2 sums close with two shuffles.  Grid: (tiles of
+// the (x, y) extent, coarse z planes, slots).
+constexpr int kMgTile = 16;
+
+__device__ __forceinline__ float mg_quad_sum(float v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, kMgTile);
+  return v;
+}
+
+// Down the V-cycle at level L (z_L = omega r_L / diag already formed):
+// r_{L+1} = P^T (r_L - A_L z_L) and the first sweep of level L + 1, z_{L+1} =
+// omega r_{L+1} / diag.  Tiled over the points of level L (above).
 static __global__ void __launch_bounds__(kBlock) k_mg_down(const MgGeom gf, const MgGeom gc,
                                                            const float4* __restrict__ op, const float* __restrict__ r,
-                                                           float* __restrict__ zo, float* __restrict__ rc, float omega,
+                                                           const float* __restrict__ zl,
+                                                           const float4* __restrict__ opc, float* __restrict__ rc,
+                                                           float* __restrict__ zc, float omega,
                                                            const DevState* __restrict__ st) {
   if (st->stop) return;
-  const int s = blockIdx.y;
-  const long long n = (long long)gc.ext[s][0] * gc.ext[s][1] * gc.ext[s][2];
-  const int fe[3] = {gf.ext[s][0], gf.ext[s][1], gf.ext[s][2]};
-  auto zf = [&](int x, int y, int z) {
-    const long long j = mg_at(gf, s, x, y, z);
-    return omega * r[j] / op[j].x;
-  };
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
-    int X, Y, Z;
-    mg_xyz(gc, s, i, X, Y, Z);
-    float acc = 0.f;
-    for (int c = 0; c < 8; ++c) {
-      const int x = 2 * X + (c & 1), y = 2 * Y + ((c >> 1) & 1), z = 2 * Z + (c >> 2);
-      if (x >= fe[0] || y >= fe[1] || z >= fe[2]) continue;
+  const int s = blockIdx.z, Z = blockIdx.y;
+  const int fx = gf.ext[s][0], fy = gf.ext[s][1], fz = gf.ext[s][2];
+  const int ntx = (fx + kMgTile - 1) / kMgTile;
+  const int x = (blockIdx.x % ntx) * kMgTile + (threadIdx.x & (kMgTile - 1));
+  const int y = (blockIdx.x / ntx) * kMgTile + (threadIdx.x / kMgTile);
+  auto zf = [&](int xx, int yy, int zz) { return zl[mg_at(gf, s, xx, yy, zz)]; };
+  float acc = 0.f;
+  if (x < fx && y < fy) {
+    for (int z = 2 * Z; z < 2 * Z + 2 && z < fz; ++z) {
       const long long j = mg_at(gf, s, x, y, z);
       const float4 o = op[j];
-      const float rv = r[j];
-      const float zv = omega * rv / o.x;
-      zo[j] = zv;
-      acc += rv - (o.x * zv + mg_offdiag(gf, s, op, o, x, y, z, zf));
+      acc += r[j] - (o.x * zl[j] + mg_offdiag(gf, s, op, o, x, y, z, zf));
     }
-    rc[gc.off[s] + i] = acc;
+  }
+  acc = mg_quad_sum(acc);
+  const int X = x >> 1, Y = y >> 1;
+  if (!(x & 1) && !(y & 1) && X < gc.ext[s][0] && Y < gc.ext[s][1] && Z < gc.ext[s][2]) {
+    const long long jc = mg_at(gc, s, X, Y, Z);
+    rc[jc] = acc;
+    zc[jc] = omega * acc * mg_rcp(opc[jc].x);
   }
 }
 
@@ -191,19 +219,19 @@ static __global__ void __launch_bounds__(kBlock) k_mg_up(const MgGeom gf, const 
                                                          const DevState* __restrict__ st) {
   if (st->stop) return;
   const int s = blockIdx.y;
-  const long long n = (long long)gf.ext[s][0] * gf.ext[s][1] * gf.ext[s][2];
+  const int n = mg_points(gf, s);
   auto zf = [&](int x, int y, int z) {
     return zl[mg_at(gf, s, x, y, z)] + zc[mg_at(gc, s, x >> 1, y >> 1, z >> 1)];
   };
   double s0 = 0.0;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     int x, y, z;
     mg_xyz(gf, s, i, x, y, z);
     const long long j = gf.off[s] + i;
     const float4 o = op[j];
     const float zp = zf(x, y, z);
     const float rv = r[j];
-    const float out = zp + omega * (rv - (o.x * zp + mg_offdiag(gf, s, op, o, x, y, z, zf))) / o.x;
+    const float out = zp + omega * (rv - (o.x * zp + mg_offdiag(gf, s, op, o, x, y, z, zf))) * mg_rcp(o.x);
     zo[j] = out;
     s0 += (double)(rv * out);
   }
@@ -218,51 +246,84 @@ static __global__ void __launch_bounds__(kBlock) k_mg_up(const MgGeom gf, const 
   }
 }
 
-// Coarsest level: `sweeps` damped Jacobi sweeps from zero, one block (the
-// level holds a few thousand points); the result ends in za.  With
-// `partials`, partials[0] = <r, z> (the coarsest level is level 1).
+// Coarsest level (at most kMgCoarseMax points, one block): `sweeps` damped
+// Jacobi sweeps from zero in LDS -- the first one, omega r / diag, formed by
+// the kernel before (in z) -- each thread keeping the neighbour indices and
+// weights of its points in registers; the result in z.  With `partials`,
+// partials[0] = <r, z> (the coarsest level is level 1).
+constexpr int kMgCoarseMax = 2048;
+constexpr int kMgCoarsePer = kMgCoarseMax / kFinBlock;
+
 static __global__ void __launch_bounds__(kFinBlock) k_mg_coarsest(const MgGeom g, const float4* __restrict__ op,
-                                                                  const float* __restrict__ r, float* __restrict__ za,
-                                                                  float* __restrict__ zb, int sweeps, float omega,
+                                                                  const float* __restrict__ r, float* __restrict__ z,
+                                                                  int sweeps, float omega,
                                                                   double* __restrict__ partials,
                                                                   const DevState* __restrict__ st) {
+  __shared__ float za[kMgCoarseMax], zb[kMgCoarseMax];
   __shared__ double red[kFinBlock / 64];
   if (st->stop) return;
-  const long long n = g.off[g.nk];
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) za[i] = omega * r[i] / op[i].x;
+  const int n = (int)g.off[g.nk];
+  int nb[kMgCoarsePer][6];
+  float w[kMgCoarsePer][6], dg[kMgCoarsePer], idg[kMgCoarsePer], rv[kMgCoarsePer];
+  for (int t = 0; t < kMgCoarsePer; ++t) {
+    const int i = threadIdx.x + t * kFinBlock;
+    dg[t] = 1.f; idg[t] = 0.f; rv[t] = 0.f;
+    for (int e = 0; e < 6; ++e) { nb[t][e] = i; w[t][e] = 0.f; }
+    if (i >= n) continue;
+    int s = 0;
+    while (s + 1 < g.nk && i >= (int)g.off[s + 1]) ++s;
+    int x, y, zz;
+    mg_xyz(g, s, i - (int)g.off[s], x, y, zz);
+    const int e3[3] = {g.ext[s][0], g.ext[s][1], g.ext[s][2]};
+    const int c3[3] = {x, y, zz};
+    const float4 o = op[i];
+    const float wp[3] = {o.y, o.z, o.w};
+    dg[t] = o.x;
+    idg[t] = mg_rcp(o.x);
+    rv[t] = r[i];
+    for (int d = 0; d < 3; ++d) {
+      const int stride = d == 0 ? 1 : (d == 1 ? e3[0] : e3[0] * e3[1]);
+      if (c3[d] + 1 < e3[d]) { nb[t][2 * d] = i + stride; w[t][2 * d] = wp[d]; }
+      if (c3[d] >= 1) {
+        const float4 om = op[i - stride];
+        nb[t][2 * d + 1] = i - stride;
+        w[t][2 * d + 1] = d == 0 ? om.y : (d == 1 ? om.z : om.w);
+      }
+    }
+    za[i] = z[i];
+  }
   __syncthreads();
   float* cur = za;
   float* nxt = zb;
-  for (int t = 1; t < sweeps; ++t) {
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
-      int s = 0;
-      while (s + 1 < g.nk && i >= g.off[s + 1]) ++s;
-      int x, y, z;
-      mg_xyz(g, s, i - g.off[s], x, y, z);
-      const float4 o = op[i];
-      auto zf = [&](int xx, int yy, int zz) { return cur[mg_at(g, s, xx, yy, zz)]; };
-      nxt[i] = cur[i] + omega * (r[i] - (o.x * cur[i] + mg_offdiag(g, s, op, o, x, y, z, zf))) / o.x;
+  for (int sw = 1; sw < sweeps; ++sw) {
+    for (int t = 0; t < kMgCoarsePer; ++t) {
+      const int i = threadIdx.x + t * kFinBlock;
+      if (i >= n) continue;
+      float az = dg[t] * cur[i];
+      for (int e = 0; e < 6; ++e) az -= w[t][e] * cur[nb[t][e]];
+      nxt[i] = cur[i] + omega * (rv[t] - az) * idg[t];
     }
     __syncthreads();
     float* tmp = cur;
     cur = nxt;
     nxt = tmp;
   }
-  if (cur != za) {
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) za[i] = cur[i];
-    __syncthreads();
+  double s0 = 0.0;
+  for (int t = 0; t < kMgCoarsePer; ++t) {
+    const int i = threadIdx.x + t * kFinBlock;
+    if (i >= n) continue;
+    z[i] = cur[i];
+    s0 += (double)(rv[t] * cur[i]);
   }
   if (partials) {
-    double s0 = 0.0, unused = 0.0;
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) s0 += (double)(r[i] * za[i]);
     s0 = wave_sum(s0);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s0;
     __syncthreads();
     if (threadIdx.x == 0) {
       double a = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += red[w];
+      for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) a += red[wv];
       partials[0] = a;
-      partials[1] = unused;
+      partials[1] = 0.0;
     }
   }
 }
@@ -340,10 +401,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_vec_mg(float* __restrict__ x, co
     const float4 rv = ld_nt(r4 + i);
     const float4 mv = ld_bf4(m4 + i);
     // lattice coordinates of the four elements
-    long long j = 4 * i;
-    int xp = (int)(j % f.PX);
-    long long t = j / f.PX;
-    int yp = (int)(t % f.PY), zp = (int)(t / f.PY);
+    const unsigned j = 4u * (unsigned)i;
+    const unsigned t = j / (unsigned)f.PX;
+    int xp = (int)(j - t * (unsigned)f.PX);
+    int zp = (int)(t / (unsigned)f.PY);
+    int yp = (int)t - zp * f.PY;
     float cz[4];
     for (int e = 0; e < 4; ++e) {
       const int xx = xp - 1, yy = yp - 1, zz = zp - 1;
