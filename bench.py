@@ -35,6 +35,7 @@ Also reported (JSON keys):
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -48,7 +49,7 @@ HBM_PEAK_GBS = 8000.0
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("pn_kernels.h", "pn_tables.h", "pn_launch.h"):
+    for f in ("pn_kernels.h", "pn_tables.h", "pn_launch.h", "pn_mg.h", "pn_mg_kernels.h"):
         with open(os.path.join(ROOT, "paper_1807_00410_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -68,21 +69,55 @@ def load_traffic(kernel_hash, kernel):
     return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
+def mg_level_points(layout):
+    """Points per level (1, 2, ...) of the multigrid preconditioner: the even
+    coefficients' lattices halved (rounding up) until every axis has at most
+    5 points and the level at most 2048 (the library's coarsening rule)."""
+    ext = [list(layout.ext[k]) for k in range(layout.ncoeff) if math.isqrt(k) % 2 == 0]  # band l = isqrt(k)
+    out = []
+    while True:
+        ext = [[(e + 1) // 2 for e in x] for x in ext]
+        out.append(sum(x[0] * x[1] * x[2] for x in ext))
+        if (max(max(x) for x in ext) <= 5 and out[-1] <= 2048) or len(out) + 1 >= 12:
+            return out
+
+
+def mg_vcycle_bytes(ne, lv):
+    """Algorithmic bytes of one V-cycle (FP32 elements, the 16-byte operator
+    {diag, w_x, w_y, w_z} per point): restriction (read fine r; read the
+    level-1 diagonal; write r_1, z_1), per level L below the coarsest a down
+    pass (read operator, r, z; read the next diagonal; write its r, z) and an
+    up pass (read operator, r, z, the coarser correction; write z), the
+    coarsest solve (read operator, r, z; write z)."""
+    b = 4 * ne + 12 * lv[0]
+    for i in range(len(lv) - 1):
+        b += 24 * lv[i] + 12 * lv[i + 1]          # down
+        b += 28 * lv[i] + 4 * lv[i + 1]           # up
+    b += 28 * lv[-1]
+    return b
+
+
 # algorithmic HBM bytes of the Krylov-loop kernels as a function of the
-# unknowns n, the even-band unknowns ne and the cells: FP32 vector elements
-# read + written, and the medium (8 B per cell) for the stencil passes
+# unknowns n, the even-band unknowns ne, the cells and the multigrid level
+# sizes: FP32 vector elements read + written, and the medium (8 B per cell)
+# for the stencil passes
 LOOP_KERNELS = (
-    ("apply", lambda n, ne, c: 8 * n + 8 * c, "k_stencil<5,float,APPLY>: y = A x"),
-    ("odd_w", lambda n, ne, c: 4 * ne + 4 * (n - ne) + 8 * c,
+    ("apply", lambda n, ne, c, lv: 8 * n + 8 * c, "k_stencil<5,float,APPLY>: y = A x"),
+    ("odd_w", lambda n, ne, c, lv: 4 * ne + 4 * (n - ne) + 8 * c,
      "k_stencil<5,float,ODD_W>: w_o = -D_o^-1 T_oe p_e (odd rows), <p, S p> partials"),
-    ("even_r", lambda n, ne, c: 4 * n + 4 * ne + 2 * ne + 4 * ne + 8 * c,
+    ("even_r", lambda n, ne, c, lv: 4 * n + 4 * ne + 2 * ne + 4 * ne + 8 * c,
      "k_stencil<5,float,EVEN_SR>: r_e -= alpha (D_e p_e + T_eo w_o) (even rows), <r, M r>, <r, r> partials"),
-    ("pcg_xp", lambda n, ne, c: 22 * ne, "k_pcg_vec<2>: x += alpha p, p = M r + beta p (M in bfloat16)"),
-    ("apply_eq", lambda n, ne, c: 8 * n + 8 * c, "k_stencil<5,float,APPLY_EQ>: q = W A p (normal-equation loop)"),
-    ("supd", lambda n, ne, c: 12 * n + 8 * c, "k_stencil<5,float,SUPD>: s -= alpha A^T q (normal-equation loop)"),
-    ("update", lambda n, ne, c: 20 * n, "k_update_xp<float>: x += alpha p, p = s + beta p (normal-equation loop)"),
+    ("mg_vcycle", lambda n, ne, c, lv: mg_vcycle_bytes(ne, lv),
+     "the V-cycle on P^T r (k_mg_restrict0, k_mg_down, k_mg_coarsest, k_mg_up), timed as one"),
+    ("pcg_xp_mg", lambda n, ne, c, lv: 22 * ne + 4 * lv[0],
+     "k_pcg_vec_mg<2>: x += alpha p, p = 0.6 M r + P z_1 + beta p (M in bfloat16)"),
+    ("pcg_xp", lambda n, ne, c, lv: 22 * ne, "k_pcg_vec<2>: x += alpha p, p = M r + beta p (Jacobi loop)"),
+    ("apply_eq", lambda n, ne, c, lv: 8 * n + 8 * c, "k_stencil<5,float,APPLY_EQ>: q = W A p (normal-equation loop)"),
+    ("supd", lambda n, ne, c, lv: 12 * n + 8 * c, "k_stencil<5,float,SUPD>: s -= alpha A^T q (normal-equation loop)"),
+    ("update", lambda n, ne, c, lv: 20 * n, "k_update_xp<float>: x += alpha p, p = s + beta p (normal-equation loop)"),
 )
-SCHUR_LOOP = ("odd_w", "even_r", "pcg_xp")
+# single kernels of the default solve's loop (the multigrid V-cycle is a group of kernels)
+DEFAULT_LOOP = ("odd_w", "even_r", "pcg_xp_mg")
 
 
 def oracle_run(tag):
@@ -380,16 +415,131 @@ def profile_kernels(args):
     ne = s.even_unknowns()
     nbytes = {name: f for name, f, _ in LOOP_KERNELS}
     nbytes["apply_t"] = nbytes["apply"]
+    lv = mg_level_points(s.layout)
+    geo = {"n": s.n, "ne": ne, "cells": cells, "mg_level_points": lv, "algorithmic_bytes": {}, "ms": {}}
     for k in args.profile_kernels.split(","):
         ms = s.bench_kernel(k, args.profile_iters)
-        alg = nbytes[k](s.n, ne, cells)
+        alg = nbytes[k](s.n, ne, cells, lv)
+        geo["algorithmic_bytes"][k] = alg
+        geo["ms"][k] = ms
         print("%s %.4f ms, %.1f GB/s algorithmic (%d unknowns)" % (k, ms, alg / ms / 1e6, s.n), flush=True)
+    print("GEOMETRY " + json.dumps(geo), flush=True)
     a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)  # calibration: 1 GiB read + 1 GiB written per copy
     torch.cuda.synchronize()
     s.close()
+
+
+# kernels of each profiled loop kernel in the rocprofv3 output (the V-cycle:
+# every kernel of the group, per V-cycle)
+PROFILE_NAMES = {
+    "apply": ("k_stencil<5, float, 0, float,",),
+    "odd_w": ("k_stencil<5, float, 6, float,",),
+    "even_r": ("k_stencil<5, float, 11, float,",),
+    "pcg_xp_mg": ("k_pcg_vec_mg<2>",),
+    "mg_vcycle": ("k_mg_restrict0", "k_mg_down", "k_mg_coarsest", "k_mg_up"),
+}
+
+
+def counters_summary(args):
+    """--counters-summary DIR: reads the outputs of the three rocprofv3 runs
+    of `bench.py --profile-kernels` (DIR/fetch, DIR/write: --pmc FETCH_SIZE /
+    WRITE_SIZE in csv; DIR/ktrace: --kernel-trace in csv, its stdout in
+    DIR/ktrace.log) and writes profiles/krylov_p5_128_counters.json and .md:
+    per loop kernel the HBM bytes per launch (counters scaled by the three
+    1 GiB copies of the same run), the algorithmic bytes and the trace's mean
+    duration.  Runs on the CPU."""
+    import csv
+    d = args.counters_summary
+    geo = None
+    with open(os.path.join(d, "ktrace.log")) as fh:
+        for line in fh:
+            if line.startswith("GEOMETRY "):
+                geo = json.loads(line[len("GEOMETRY "):])
+    rows = {c: list(csv.DictReader(open(os.path.join(d, c, c + "_counter_collection.csv")))) for c in ("fetch", "write")}
+    trace = list(csv.DictReader(open(os.path.join(d, "ktrace", "ktrace_kernel_trace.csv"))))
+    cal = {}
+    for c in ("fetch", "write"):
+        big = sorted(float(r["Counter_Value"]) for r in rows[c] if "copyBuffer" in r["Kernel_Name"])[-3:]
+        cal[c] = (1 << 30) / (sum(big) / len(big) * 1024.0)
+    out = {"workload": "P5 nebula 128^3, zchunk 2", "source_hash": source_hash(), "fetch_factor": cal["fetch"],
+           "write_factor": cal["write"], "summary": "profiles/krylov_p5_128_counters.md", "kernels": {}}
+    for name, pats in PROFILE_NAMES.items():
+        if name not in geo["algorithmic_bytes"]:
+            continue
+        match = lambda kn: any(p in kn for p in pats)
+        launches = sum(1 for r in rows["fetch"] if pats[0] in r["Kernel_Name"])
+        tot = {c: sum(float(r["Counter_Value"]) for r in rows[c] if match(r["Kernel_Name"])) for c in rows}
+        durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace if match(r["Kernel_Name"])]
+        ntrace = sum(1 for r in trace if pats[0] in r["Kernel_Name"])
+        hf = tot["fetch"] / launches * 1024 * cal["fetch"]
+        hw = tot["write"] / launches * 1024 * cal["write"]
+        alg = geo["algorithmic_bytes"][name]
+        out["kernels"][name] = {"kernels": list(pats), "launches": launches,
+                                "fetch_KiB_per_launch": tot["fetch"] / launches,
+                                "write_KiB_per_launch": tot["write"] / launches,
+                                "hbm_fetch_bytes_per_launch": hf, "hbm_write_bytes_per_launch": hw,
+                                "hbm_bytes_per_launch": hf + hw, "algorithmic_bytes_per_launch": alg,
+                                "traffic_over_algorithmic": (hf + hw) / alg,
+                                "mean_us_trace": sum(durs) / max(ntrace, 1) / 1e3}
+    with open(os.path.join(ROOT, "profiles", "krylov_p5_128_counters.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    cmd = "python3 bench.py --profile-kernels " + ",".join(geo["algorithmic_bytes"])
+    lines = ["# Krylov-loop kernels, P5 128^3: HBM traffic counters (rocprofv3 --pmc)", "",
+             "Commands (from the repository root, `TMPDIR=/tmp`; `bench.py --profile-kernels` runs each listed",
+             "loop kernel of the nebula workload in its in-loop form, 1 warm-up + 10 timed iterations at",
+             "zchunk 2, then three 1 GiB device copies that calibrate the counters):", "",
+             "    timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/fetch -o fetch -- \\",
+             "        " + cmd,
+             "    timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/write -o write -- \\",
+             "        " + cmd,
+             "    timeout -k 10 150 rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/ktrace -o ktrace -- \\",
+             "        " + cmd + " > gpurun_out/prof/ktrace.log",
+             "    python3 bench.py --counters-summary gpurun_out/prof      # this file and its .json", "",
+             "Calibration (the three 1 GiB `copyBuffer` dispatches): HBM bytes = FETCH_SIZE x 1024 x %.3f and"
+             % cal["fetch"], "WRITE_SIZE x 1024 x %.3f.  The V-cycle row sums all kernels of one V-cycle "
+             "(restriction, %d down passes, coarsest solve, %d up passes)." % (cal["write"], len(geo["mg_level_points"]) - 1,
+                                                                              len(geo["mg_level_points"]) - 1), "",
+             "| loop kernel | launches | HBM read MB | HBM write MB | algorithmic MB | traffic / algorithmic | trace mean us | algorithmic GB/s |",
+             "|---|---|---|---|---|---|---|---|"]
+    for name, k in out["kernels"].items():
+        lines.append("| %s | %d | %.1f | %.1f | %.1f | %.2f | %.1f | %.0f |" % (
+            name, k["launches"], k["hbm_fetch_bytes_per_launch"] / 1e6, k["hbm_write_bytes_per_launch"] / 1e6,
+            k["algorithmic_bytes_per_launch"] / 1e6, k["traffic_over_algorithmic"], k["mean_us_trace"],
+            k["algorithmic_bytes_per_launch"] / k["mean_us_trace"] / 1e3))
+    lines += ["", "Geometry: n = %d unknowns, ne = %d in the even bands, %d cells; multigrid level points %s." % (
+        geo["n"], geo["ne"], geo["cells"], geo["mg_level_points"]),
+        "Algorithmic bytes: see `LOOP_KERNELS` and `mg_vcycle_bytes` in bench.py.",
+        "", "Kernel source hash (pn_kernels.h, pn_tables.h, pn_launch.h, pn_mg.h, pn_mg_kernels.h): %s" % out["source_hash"]]
+    with open(os.path.join(ROOT, "profiles", "krylov_p5_128_counters.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    solve_stats = os.path.join(d, "solve", "solve_kernel_stats.csv")
+    if os.path.exists(solve_stats):
+        stats = list(csv.DictReader(open(solve_stats)))
+        log = open(os.path.join(d, "solve.log")).read().strip().splitlines() if os.path.exists(
+            os.path.join(d, "solve.log")) else []
+        sl = ["# P5 128^3 nebula solve: kernel time (rocprofv3 kernel trace)", "",
+              "Command (from the repository root, `TMPDIR=/tmp`):", "",
+              "    timeout -k 10 150 rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/solve "
+              "-o solve -- \\", "        python3 bench.py --profile-solve --profile-iters 2 > gpurun_out/prof/solve.log",
+              "    python3 bench.py --counters-summary gpurun_out/prof", "",
+              "Three solves (one untimed, two profiled) of the P5 128^3 nebula (76,237,059 unknowns, 31,753,344 in "
+              "the even bands) with the default solver: the even-parity PCG with the multigrid preconditioner, "
+              "FP32 vectors, FP64 dots and refinement, tol 1e-8, inner_tol 1e-2, zchunk 2.  The program's "
+              "output:", ""] + ["    " + x for x in log if x.startswith("solve ")] + [
+              "", "All dispatches (loop kernels launched after a solve's stop flag return at once and pull the "
+              "averages down; each captured graph holds 32 iterations):", "",
+              "| kernel | calls | total ms | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|---|"]
+        for r in stats[:20]:
+            nm = r["Name"].split("(")[0]
+            sl.append("| `%s` | %s | %.2f | %.1f | %.1f | %.1f | %.1f |" % (
+                nm, r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+                float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+        with open(os.path.join(ROOT, "profiles", "solve_p5_128_kernel_stats.md"), "w") as fh:
+            fh.write("\n".join(sl) + "\n")
 
 
 def profile_solve(args):
@@ -476,6 +626,8 @@ def main():
                          "apply_eq, supd, update) "
                          "run in their in-loop form for rocprofv3, then the counter-calibration copies")
     ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--counters-summary", default=None, metavar="DIR",
+                    help="write profiles/krylov_p5_128_counters.{json,md} from the rocprofv3 outputs in DIR")
     ap.add_argument("--profile-solve", action="store_true",
                     help="solve the P5 nebula 1 + --profile-iters times with the default solver, nothing else "
                          "(the kernel trace of a real solve for rocprofv3)")
@@ -492,6 +644,9 @@ def main():
         return
     if args.profile_solve:
         profile_solve(args)
+        return
+    if args.counters_summary:
+        counters_summary(args)
         return
     if args.accuracy:
         accuracy_check(args)
@@ -550,18 +705,25 @@ def main():
     khash = source_hash()
     loop = {}
     ne = s.even_unknowns()
+    lv = mg_level_points(s.layout)
     for name, nbytes, desc in LOOP_KERNELS:
         ms = s.bench_kernel(name, args.apply_iters)
-        alg = nbytes(s.n, ne, cells)
+        alg = nbytes(s.n, ne, cells, lv)
         ach = alg / (ms * 1e-3) / 1e9
         loop[name] = {"kernel": desc, "ms": ms, "algorithmic_bytes_per_launch": alg, "achieved": ach,
                       "frac": ach / HBM_PEAK_GBS, "traffic": load_traffic(khash, name)}
         print("[bench] %-8s %.4f ms  %.0f GB/s algorithmic" % (name, ms, ach), file=sys.stderr, flush=True)
     # the dominant kernel: the most time per iteration of the default (even-parity) solve
-    dom = max(SCHUR_LOOP, key=lambda k: loop[k]["ms"])
+    dom = max(DEFAULT_LOOP, key=lambda k: loop[k]["ms"])
 
-    # the previous default inner solver (CG on the row-equilibrated normal
-    # equations) on the same system
+    # the even-parity PCG with the Jacobi preconditioner alone
+    tj, ij = timed_solve(s, rhs, torch.zeros_like(x), warmup=0, tol=args.tol, inner_tol=args.inner_tol,
+                         variant="schur")
+    jac = {"seconds": tj, "iters": ij["inner_iters"], "rel_residual": ij["rel_residual"],
+           "speedup_of_default": tj / sec}
+    print("[bench] even-parity PCG, Jacobi preconditioner: %.3fs iters %d" % (tj, ij["inner_iters"]),
+          file=sys.stderr, flush=True)
+    # CG on the row-equilibrated normal equations on the same system
     ti, ii = timed_solve(s, rhs, torch.zeros_like(x), warmup=0, tol=args.tol, inner_tol=args.inner_tol,
                          variant="cg_eq")
     cg_eq = {"seconds": ti, "iters": ii["inner_iters"], "rel_residual": ii["rel_residual"],
@@ -635,8 +797,9 @@ def main():
         "config": {"workload": "P%d nebula %d^3 (32 Gaussian blobs x fBm, sigma_t in [0,200], albedo 0.95, "
                                "g=%g, 2 point sources), vacuum boundary, tol %g"
                                % (m.order, args.n, m.g, args.tol),
-                   "unknowns": s.n, "solver": "FP32 even-parity PCG (Jacobi-preconditioned CG on the Schur complement "
-                                             "of the even bands) + FP64 dots/refinement (plain)",
+                   "unknowns": s.n, "solver": "FP32 even-parity PCG (CG on the Schur complement of the even bands, "
+                                             "preconditioner 0.6 Jacobi + one aggregation V-cycle per even "
+                                             "coefficient) + FP64 dots/refinement (plain)",
                    "inner_tol": args.inner_tol, "zchunk": zchunk},
         "iters": infos[-1]["inner_iters"],
         "outer_iters": infos[-1]["outer_iters"],
@@ -646,6 +809,7 @@ def main():
         "apply_t_ms": ms_apply_t,
         "phases_ms": infos[-1]["t_ms"], "solve_algorithmic_bytes": infos[-1]["bytes"],
         "solve_achieved_GBs": infos[-1]["achieved_gbs"],
+        "even_parity_jacobi": jac,
         "cg_eq_normal_equations": cg_eq,
         "fp64_krylov": fp64,
         "fp32_krylov_no_refinement": fp32_single,

@@ -142,7 +142,7 @@ typedef struct {
  * Jacobi one.  S couples every even coefficient to itself only at the six
  * lattice neighbours (a weighted diffusion operator per coefficient, the
  * band-l form of the diffusion equation that P1 collapses to, section
- * "Results"), so B r = 0.7 M r + P V(P^T r): M the Jacobi inverse diagonal,
+ * "Results"), so B r = 0.6 M r + P V(P^T r): M the Jacobi inverse diagonal,
  * P the piecewise-constant prolongation over 2 x 2 x 2 aggregates of each
  * coefficient's lattice and V one V-cycle on the Galerkin coarse operators
  * (damped Jacobi smoothing, coarsening down to at most 5 points per axis).
@@ -329,10 +329,17 @@ pn_status pn_bench_apply(pn_ctx* ctx, int iters, int transpose, double* ms_per_a
  *                        partials of <p, S p> = <p_e, D_e p_e> + <w_o, D_o w_o>
  *   PN_KERNEL_EVEN_R     r_e -= alpha (D_e p_e + T_eo w_o) (even rows) with
  *                        <r, M r>, <r, r>
- *   PN_KERNEL_PCG_XP     x += alpha p, p = M r + beta p */
+ *   PN_KERNEL_PCG_XP     x += alpha p, p = M r + beta p
+ * and of its multigrid form (PN_VARIANT_SCHUR_MG; vacuum boundary on every
+ * axis, PN_ERR_ARG otherwise), inside odd rows | even rows | V-cycle | x/p:
+ *   PN_KERNEL_MG_VCYCLE  the whole V-cycle on P^T r (restriction, down and up
+ *                        passes of every level, coarsest solve), timed as one
+ *   PN_KERNEL_PCG_XP_MG  x += alpha p, p = omega_f M r + P z_1 + beta p */
 #define PN_KERNEL_ODD_W 5
 #define PN_KERNEL_EVEN_R 6
 #define PN_KERNEL_PCG_XP 7
+#define PN_KERNEL_MG_VCYCLE 8
+#define PN_KERNEL_PCG_XP_MG 9
 pn_status pn_bench_kernel(pn_ctx* ctx, int kernel, int iters, double* ms);
 
 /* Launch tuning: planes of z handled per thread block in the stencil apply

@@ -733,12 +733,24 @@ extern "C" pn_status pn_bench_apply(pn_ctx* c, int iters, int transpose, double*
 // next solve re-initialises them.
 static int pcg_vec_blocks(const pn_ctx* c);
 
+static bool mg_ok(const pn_ctx* c);
+static pn_status schur_prepare(pn_ctx* c, bool mg, hipStream_t st);
+static hipError_t mg_vcycle(pn_ctx* c, const float* r, hipStream_t st);
+static const float* mg_final(const pn_ctx* c, int L);
+constexpr float kMgOmegaFine = 0.6f;  // weight of the Jacobi part of B
+
 extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* ms) {
-  if (!c || iters < 1 || !ms || kernel < PN_KERNEL_APPLY || kernel > PN_KERNEL_PCG_XP)
+  if (!c || iters < 1 || !ms || kernel < PN_KERNEL_APPLY || kernel > PN_KERNEL_PCG_XP_MG)
     return c ? fail(c, PN_ERR_ARG, "bad arguments") : PN_ERR_ARG;
   if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
   if (c->use_lds && kernel != PN_KERNEL_APPLY && kernel != PN_KERNEL_APPLY_T)
     return fail(c, PN_ERR_ARG, "the in-loop kernels are timed on the register-window stencil");
+  const bool mgk = kernel >= PN_KERNEL_MG_VCYCLE;
+  if (mgk) {
+    if (!mg_ok(c)) return fail(c, PN_ERR_ARG, "the multigrid kernels need the vacuum boundary on every axis");
+    pn_status e = schur_prepare(c, true, c->stream);  // Jacobi diagonal and multigrid operators
+    if (e != PN_OK) return e;
+  }
   DevState init;
   std::memset(&init, 0, sizeof(init));
   init.alpha = 0.5;
@@ -776,6 +788,15 @@ extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* m
                            (const float*)c->q32, (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
         return hipGetLastError();
       }
+      case PN_KERNEL_MG_VCYCLE:
+        return mg_vcycle(c, c->r32[1], c->stream);
+      case PN_KERNEL_PCG_XP_MG: {
+        const dim3 vg(pcg_vec_blocks(c), c->even.nk);
+        hipLaunchKernelGGL(k_pcg_vec_mg<2>, vg, dim3(kBlock), 0, c->stream, c->d32, (const float*)c->r32[1], c->p32,
+                           (const uint16_t*)c->m16, c->mg_fine, c->mg_geom[1], mg_final(c, 1), kMgOmegaFine,
+                           (const DevState*)c->st);
+        return hipGetLastError();
+      }
       default:
         hipLaunchKernelGGL((k_update_xp<float>), dim3(stream_grid(c->nv / 4)), dim3(kBlock), 0, c->stream, c->d32,
                            c->p32, (const float*)c->s32, (long)c->nv, (const DevState*)c->st);
@@ -793,12 +814,14 @@ extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* m
     PN_HIP(hipEventElapsedTime(&t, e0, e1));
     total = t;
   } else {
-    const int seq_cg[3] = {PN_KERNEL_APPLY_EQ, PN_KERNEL_SUPD, PN_KERNEL_UPDATE};
-    const int seq_schur[3] = {PN_KERNEL_ODD_W, PN_KERNEL_EVEN_R, PN_KERNEL_PCG_XP};
-    const bool sc = kernel >= PN_KERNEL_ODD_W;
+    const int seq_cg[4] = {PN_KERNEL_APPLY_EQ, PN_KERNEL_SUPD, PN_KERNEL_UPDATE, -1};
+    const int seq_schur[4] = {PN_KERNEL_ODD_W, PN_KERNEL_EVEN_R, PN_KERNEL_PCG_XP, -1};
+    const int seq_mg[4] = {PN_KERNEL_ODD_W, PN_KERNEL_EVEN_R, PN_KERNEL_MG_VCYCLE, PN_KERNEL_PCG_XP_MG};
+    const int* seq = mgk ? seq_mg : (kernel >= PN_KERNEL_ODD_W ? seq_schur : seq_cg);
     for (int i = 0; i <= iters; ++i) {  // iteration 0 warms up
-      for (int j = 0; j < 3; ++j) {
-        const int k = sc ? seq_schur[j] : seq_cg[j];
+      for (int j = 0; j < 4; ++j) {
+        const int k = seq[j];
+        if (k < 0) break;
         if (k == kernel) PN_HIP(hipEventRecord(e0, c->stream));
         PN_HIP(launch(k));
         if (k == kernel) PN_HIP(hipEventRecord(e1, c->stream));
@@ -946,8 +969,7 @@ static bool schur_ok(const pn_ctx* c) {
 // ------------------------------------------------ multigrid preconditioner --
 // B r = omega_f M r + P V(P^T r) (see pn_mg.h), on contexts with the vacuum
 // boundary on every axis (aggregation over the class extents).
-constexpr float kMgOmegaFine = 0.7f;  // weight of the Jacobi part of B
-constexpr float kMgOmega = 0.7f;      // damped Jacobi on the coarse levels
+constexpr float kMgOmega = 0.9f;      // damped Jacobi on the coarse levels
 constexpr int kMgSweeps = 16;         // damped Jacobi sweeps on the coarsest level
 constexpr int kMgCoarsest = 5;        // coarsen until every axis has at most this many points
 
@@ -1055,6 +1077,27 @@ static dim3 mg_tiles(const MgGeom& f, const MgGeom& c) {
     zc = std::max(zc, c.ext[s][2]);
   }
   return dim3(tx * ty, zc, f.nk);
+}
+
+// Preconditioner setup of the even-parity solve: 1 / d_o in the odd slots of
+// q32 (d32 = 0, x2 = NULL reads as 1), m = 1 / diag(S) in the even slots of
+// s32 and its bfloat16 copy m16; with `mg`, the multigrid operators.
+static pn_status schur_prepare(pn_ctx* c, bool mg, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(c->nv)), dim3(kBlock), 0, st, c->d32, (long)c->nv, 0.f);
+  PN_HIP(hipGetLastError());
+  StencilArgs a = base_args(c);
+  a.x = c->d32; a.x2 = nullptr; a.y = c->q32;
+  PN_HIP((launch_stencil<float, M_ODD_BACK, float>(c, a, st)));
+  a.x = c->q32; a.y = c->s32;
+  PN_HIP((launch_stencil<float, M_EVEN_JAC, float>(c, a, st)));
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(c->nv)), dim3(kBlock), 0, st, (const float*)c->s32, c->m16, (long)c->nv);
+  PN_HIP(hipGetLastError());
+  if (mg) {
+    pn_status e = mg_alloc(c);
+    if (e == PN_OK) e = mg_setup_ops(c, c->s32, c->q32, st);
+    if (e != PN_OK) return e;
+  }
+  return PN_OK;
 }
 
 static const float* mg_final(const pn_ctx* c, int L) { return L == c->mg_levels ? c->mg_z[L] : c->mg_zt[L]; }
@@ -1370,22 +1413,8 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
   }
   const dim3 vg(pcg_vec_blocks(c), c->even.nk);
   if (schur) {
-    // Jacobi preconditioner: 1 / d_o in the odd slots of q32 (d32 = 0, x2 =
-    // NULL reads as 1), then m = 1 / diag(S) in the even slots of s32
-    hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(c->nv)), dim3(kBlock), 0, c->sstream, c->d32, (long)c->nv, 0.f);
-    PN_HIP(hipGetLastError());
-    StencilArgs a = base_args(c);
-    a.x = c->d32; a.x2 = nullptr; a.y = c->q32;
-    PN_HIP((launch_stencil<float, M_ODD_BACK, float>(c, a, c->sstream)));
-    a.x = c->q32; a.y = c->s32;
-    PN_HIP((launch_stencil<float, M_EVEN_JAC, float>(c, a, c->sstream)));
-    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(c->nv)), dim3(kBlock), 0, c->sstream, (const float*)c->s32, c->m16,
-                       (long)c->nv);
-    PN_HIP(hipGetLastError());
-    if (mg) {
-      pn_status e = mg_setup_ops(c, c->s32, c->q32, c->sstream);
-      if (e != PN_OK) return e;
-    }
+    pn_status e = schur_prepare(c, mg, c->sstream);
+    if (e != PN_OK) return e;
   }
   hipStream_t ss = c->sstream;
   DevState init;

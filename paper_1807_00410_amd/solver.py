@@ -148,7 +148,7 @@ class Solver:
                                            _ptr(r, torch.float64) if r is not None else None, C.byref(rel)))
         return rel.value
 
-    KERNELS = {"apply": 0, "apply_t": 1, "apply_eq": 2, "supd": 3, "update": 4,
+    KERNELS = {"apply": 0, "apply_t": 1, "apply_eq": 2, "supd": 3, "update": 4, "mg_vcycle": 8, "pcg_xp_mg": 9,
                "odd_w": 5, "even_r": 6, "pcg_xp": 7}
 
     def bench_kernel(self, kernel, iters=20):

@@ -1,5 +1,5 @@
 """GPU parity of the even-parity PCG with the multigrid preconditioner
-(PN_VARIANT_SCHUR_MG, AUTO on vacuum boundaries): B r = 0.7 M r + P V(P^T r),
+(PN_VARIANT_SCHUR_MG, AUTO on vacuum boundaries): B r = 0.6 M r + P V(P^T r),
 one aggregation V-cycle per even coefficient on the Galerkin coarse
 operators of the Schur complement's diagonal blocks.
 
