@@ -584,7 +584,9 @@ def accuracy_check(args):
                    sigma_t_min=m.sigma_t_min)
         rhs = s.rhs_from_q00(torch.as_tensor(m.q00[0]).cuda())
         res = {}
-        for name, kw in (("even-parity PCG (default)", {}), ("CG, equilibrated normal equations", {"variant": "cg_eq"}),
+        for name, kw in (("even-parity PCG, multigrid (default)", {}),
+                         ("even-parity PCG, Jacobi", {"variant": "schur"}),
+                         ("CG, equilibrated normal equations", {"variant": "cg_eq"}),
                          ("CGLS in FP64", {"precision": "fp64"})):
             x, info = s.solve(rhs, tol=args.tol, **kw)
             xs = x.cpu().numpy()
