@@ -246,6 +246,18 @@ pn_status pn_apply(pn_ctx* ctx, const float* x, float* y, int transpose);
  * solve does not use S).  Asynchronous on the context stream. */
 pn_status pn_apply_schur(pn_ctx* ctx, const float* x, float* y);
 
+/* The preconditioner of the even-parity solve applied to r: z_e = B r_e on
+ * the even-band entries, z_o = 0.  variant PN_VARIANT_SCHUR: B = M, the
+ * Jacobi inverse diagonal of S (bfloat16); PN_VARIANT_SCHUR_MG: B = 0.6 M +
+ * P V P^T, the multigrid form (see the variants below; vacuum boundary on
+ * every axis).  B is symmetric positive definite and depends on the medium
+ * only; it is formed at the first call (or solve) and kept.  r, z: device
+ * FP32 packed vectors (n_unknowns), not overlapping.  Overwrites the Krylov
+ * workspace (a following pn_solve re-initialises it).  PN_ERR_ARG for another
+ * variant, a Neumann axis, zero extinction, or (MG) a non-vacuum axis.
+ * Asynchronous on the context stream. */
+pn_status pn_apply_precond(pn_ctx* ctx, int variant, const float* r, float* z);
+
 /* Single-scattered light of a point light folded into the emission term
  * (section "Rendering"): writes rhs (DEVICE FP32, packed layout, n_unknowns
  * entries) with, at the location y of every unknown (coefficient k = (l, m)),

@@ -80,6 +80,7 @@ SIGNATURES = [
     ("pn_bench_kernel", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     ("pn_row_weights", C.c_int, [C.c_void_p, C.c_void_p]),
     ("pn_apply_schur", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pn_apply_precond", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     ("pn_single_scatter", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_double, C.c_void_p]),
     ("pn_unstagger", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pn_set_tiles", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),

@@ -592,6 +592,12 @@ extern "C" pn_status pn_apply(pn_ctx* c, const float* x, float* y, int transpose
 }
 
 static bool schur_ok(const pn_ctx* c);
+static int pcg_vec_blocks(const pn_ctx* c);
+static bool mg_ok(const pn_ctx* c);
+static pn_status schur_prepare(pn_ctx* c, bool mg, hipStream_t st);
+static hipError_t mg_vcycle(pn_ctx* c, const float* r, hipStream_t st);
+static const float* mg_final(const pn_ctx* c, int L);
+constexpr float kMgOmegaFine = 0.6f;  // weight of the Jacobi part of B
 
 static RenderArgs render_args(const pn_ctx* c) {
   RenderArgs a;
@@ -665,6 +671,42 @@ extern "C" pn_status pn_apply_schur(pn_ctx* c, const float* x, float* y) {
   return PN_OK;
 }
 
+extern "C" pn_status pn_apply_precond(pn_ctx* c, int variant, const float* r, float* z) {
+  if (!c) return PN_ERR_ARG;
+  if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
+  if (!r || !z) return fail(c, PN_ERR_ARG, "r or z is NULL");
+  if ((const void*)r == (const void*)z) return fail(c, PN_ERR_ARG, "r and z must not alias");
+  if (variant != PN_VARIANT_SCHUR && variant != PN_VARIANT_SCHUR_MG)
+    return fail(c, PN_ERR_ARG, "variant must be PN_VARIANT_SCHUR or PN_VARIANT_SCHUR_MG");
+  const bool mg = variant == PN_VARIANT_SCHUR_MG;
+  if (!schur_ok(c)) return fail(c, PN_ERR_ARG, "the even-parity preconditioner needs no Neumann axis and positive extinction");
+  if (mg && !mg_ok(c)) return fail(c, PN_ERR_ARG, "the multigrid preconditioner needs the vacuum boundary on every axis");
+  const int need = mg ? 3 : 1;
+  if ((c->prec_ready & need) != need) {
+    pn_status e = schur_prepare(c, mg, c->stream);
+    if (e != PN_OK) return e;
+  }
+  DevState init;
+  std::memset(&init, 0, sizeof(init));
+  PN_HIP(hipMemcpyAsync(c->st, &init, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  PN_HIP((launch_pack<float, float, 0>(c, r, c->r32[1], c->stream)));
+  hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(c->nv)), dim3(kBlock), 0, c->stream, c->p32, (long)c->nv, 0.f);
+  PN_HIP(hipGetLastError());
+  const dim3 vg(pcg_vec_blocks(c), c->even.nk);
+  if (mg) {
+    PN_HIP(mg_vcycle(c, c->r32[1], c->stream));
+    hipLaunchKernelGGL(k_pcg_vec_mg<4>, vg, dim3(kBlock), 0, c->stream, c->d32, (const float*)c->r32[1], c->p32,
+                       (const uint16_t*)c->m16, c->mg_fine, c->mg_geom[1], mg_final(c, 1), kMgOmegaFine,
+                       (const DevState*)c->st);
+  } else {
+    hipLaunchKernelGGL(k_pcg_vec<0>, vg, dim3(kBlock), 0, c->stream, c->d32, c->r32[1], c->p32, (const float*)c->q32,
+                       (const uint16_t*)c->m16, c->even, c->partials, (const DevState*)c->st);
+  }
+  PN_HIP(hipGetLastError());
+  PN_HIP((launch_pack<float, float, 1>(c, c->p32, z, c->stream)));
+  return PN_OK;
+}
+
 extern "C" pn_status pn_row_weights(pn_ctx* c, float* w) {
   if (!c) return PN_ERR_ARG;
   if (!c->p32) return fail(c, PN_ERR_ARG, "context has no Krylov workspace (a batch problem context)");
@@ -731,13 +773,7 @@ extern "C" pn_status pn_bench_apply(pn_ctx* c, int iters, int transpose, double*
 // sees in a solve; events around the requested kernel give its mean time.
 // The device scalars are reset first (alpha = beta = 0.5, no stop flag); the
 // next solve re-initialises them.
-static int pcg_vec_blocks(const pn_ctx* c);
 
-static bool mg_ok(const pn_ctx* c);
-static pn_status schur_prepare(pn_ctx* c, bool mg, hipStream_t st);
-static hipError_t mg_vcycle(pn_ctx* c, const float* r, hipStream_t st);
-static const float* mg_final(const pn_ctx* c, int L);
-constexpr float kMgOmegaFine = 0.6f;  // weight of the Jacobi part of B
 
 extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* ms) {
   if (!c || iters < 1 || !ms || kernel < PN_KERNEL_APPLY || kernel > PN_KERNEL_PCG_XP_MG)
@@ -1092,10 +1128,12 @@ static pn_status schur_prepare(pn_ctx* c, bool mg, hipStream_t st) {
   PN_HIP((launch_stencil<float, M_EVEN_JAC, float>(c, a, st)));
   hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(c->nv)), dim3(kBlock), 0, st, (const float*)c->s32, c->m16, (long)c->nv);
   PN_HIP(hipGetLastError());
+  c->prec_ready |= 1;
   if (mg) {
     pn_status e = mg_alloc(c);
     if (e == PN_OK) e = mg_setup_ops(c, c->s32, c->q32, st);
     if (e != PN_OK) return e;
+    c->prec_ready |= 2;
   }
   return PN_OK;
 }

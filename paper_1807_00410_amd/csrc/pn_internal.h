@@ -105,6 +105,7 @@ struct pn_ctx {
   float* mg_zt[kMgMaxLevels] = {};
   double* mg_partials = nullptr;
   int mg_npart = 0;  // block partial pairs of <P^T r, V(P^T r)>
+  int prec_ready = 0;  // bit 0: m16 formed, bit 1: the multigrid operators formed
   hipGraphExec_t gexec_mg = nullptr;
   int giters_mg = 0;
   int giters_cg = 0;

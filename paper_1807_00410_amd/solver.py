@@ -125,6 +125,15 @@ class Solver:
         self._check(self.lib.pn_unstagger(self.ctx, _ptr(x, torch.float64), C.c_void_p(out.data_ptr())))
         return out
 
+    def apply_precond(self, r, variant="schur_mg", z=None):
+        """z = B r on the even-band entries (0 elsewhere): the Jacobi (variant
+        "schur") or multigrid ("schur_mg") preconditioner of the even-parity
+        solve (pn_apply_precond)."""
+        z = torch.empty_like(r) if z is None else z
+        code = {"schur": 4, "schur_mg": 5}.get(variant, variant)  # or a PN_VARIANT_* code
+        self._check(self.lib.pn_apply_precond(self.ctx, code, _ptr(r, torch.float32), _ptr(z, torch.float32)))
+        return z
+
     def apply_schur(self, x, y=None):
         """y_o = -D_o^-1 T_oe x_e and y_e = S x_e (pn_apply_schur); x packed FP32."""
         y = torch.empty_like(x) if y is None else y

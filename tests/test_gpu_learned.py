@@ -157,3 +157,88 @@ def test_targets_of_a_difference_match_targets_of_the_difference():
     assert torch.equal(t1, t2)
     assert torch.equal(s.net_targets(a, sub=None), s.net_targets(a))
     s.close()
+
+
+def _net_solution(s, net, src, n_ext):
+    """The network's prediction of A^-1 src (packed, P3 coefficients at the
+    lattice points with the cell's indices; the amplitude is arbitrary)."""
+    y = net.forward(s.net_features(src))[0]
+    nx, ny, nz = s.layout.dims
+    u = torch.zeros(s.n, dtype=torch.float32, device=src.device)
+    for k in range(16):
+        ex, ey, ez = s.layout.ext[k]
+        v = u[s.layout.offset[k]:s.layout.offset[k + 1]].view(ez, ey, ex)
+        v[:min(ez, nz), :min(ey, ny), :min(ex, nx)] = y[:nz, :ny, :nx, k][:min(ez, nz), :min(ey, ny), :min(ex, nx)]
+    return u
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained weights in the tree")
+def test_flexible_cg_with_the_network_in_the_preconditioner():
+    # ablation: the trained network as part of a variable preconditioner
+    # M(r) = B r + gamma N(r) (B the multigrid preconditioner, N(r) the
+    # network's prediction of the even-parity correction for residual r,
+    # gamma the step minimising the S-norm error along it) inside flexible CG
+    # (each new direction S-orthogonalised against the previous one) on the
+    # even-parity system of a held-out P3 64^3 medium, against the same
+    # flexible CG with B alone; the network applied every iteration or every
+    # 8th.  Vectors in FP32 (the library's operators), dots in FP64; stop at
+    # ||r|| <= 1e-5 ||f||.  Prints iterations and time of each.
+    import time
+    from paper_1807_00410_amd.net import Net
+    m = config_p3_fbm(n=64, seed=90001, order=3)
+    s = solver(m)
+    net = Net(seed=0)
+    net.load(WEIGHTS)
+    lay = s.layout
+    even = torch.zeros(s.n, dtype=torch.float32, device="cuda")
+    for k in range(lay.ncoeff):
+        if int(np.sqrt(k)) % 2 == 0:
+            even[lay.offset[k]:lay.offset[k + 1]] = 1.0
+    f = s.rhs_from_q00(dev(m.q00[0])) * even  # Q has l = 0 only: the reduced right-hand side is Q_e
+    fn = f.double().norm().item()
+    S = lambda v: s.apply_schur(v) * even
+
+    def fcg(every, max_it=3000):
+        x = torch.zeros_like(f)
+        r = f.clone()
+        p_prev = q_prev = None
+        t0 = time.perf_counter()
+        net_calls = 0
+        for it in range(1, max_it + 1):
+            z = s.apply_precond(r)
+            if every and (it - 1) % every == 0:
+                n = _net_solution(s, net, r, lay) * even
+                sn = S(n)
+                den = float(n.double() @ sn.double())
+                if den > 0:
+                    z = z + (float(n.double() @ r.double()) / den) * n
+                net_calls += 1
+            p = z
+            if p_prev is not None:
+                p = z - (float(z.double() @ q_prev.double()) / float(p_prev.double() @ q_prev.double())) * p_prev
+            q = S(p)
+            a = float(p.double() @ r.double()) / float(p.double() @ q.double())
+            x = x + a * p
+            r = r - a * q
+            p_prev, q_prev = p, q
+            if r.double().norm().item() <= 1e-5 * fn:
+                break
+        torch.cuda.synchronize()
+        return x, it, time.perf_counter() - t0, net_calls
+
+    fcg(1, max_it=3)  # warm-up: operator setup, network buffers
+    x_b, it_b, t_b, _ = fcg(0)
+    x_1, it_1, t_1, c_1 = fcg(1)
+    x_8, it_8, t_8, c_8 = fcg(8)
+    print("flexible CG, B only:            %4d iterations %.3f s" % (it_b, t_b))
+    print("flexible CG, B + network each:  %4d iterations %.3f s (%d network calls)" % (it_1, t_1, c_1))
+    print("flexible CG, B + network / 8:   %4d iterations %.3f s (%d network calls)" % (it_8, t_8, c_8))
+    print("one iteration %.2f ms, one network step (prediction + S-norm scaling) %.2f ms" % (
+        1e3 * t_b / it_b, 1e3 * (t_1 - t_b * it_1 / it_b) / c_1))
+    for xx, it in ((x_b, it_b), (x_1, it_1), (x_8, it_8)):
+        assert it < 3000
+        assert (xx - x_b).double().norm().item() <= 1e-3 * x_b.double().norm().item()
+    # the network never makes the flexible iteration take more steps here
+    assert it_1 <= it_b + 2 and it_8 <= it_b + 2
+    s.close()
+    net.close()

@@ -122,3 +122,40 @@ def test_mg_repeated_solves_and_warm_start():
     s.close()
     xs = x3.cpu().numpy()
     assert i3["status"] == 0 and np.linalg.norm(b - A @ xs) / np.linalg.norm(b) <= 1.01e-10
+
+
+def test_apply_precond_definitions():
+    # Jacobi: z_e = bf16(1 / diag(S)) r_e with diag(S) from the oracle's
+    # matrix, z_o = 0; multigrid: B symmetric positive definite and linear
+    import scipy.sparse as sp
+    from oracle.sh import coeff_lm
+    m = config_small(5, (9, 8, 7), seed=11, sigma_range=(1.0, 30.0), sigma_t_min=1.0)
+    A, lay = assemble(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min)
+    par = np.concatenate([np.full(lay.size[k], coeff_lm(k)[0] % 2) for k in range(lay.ncoeff)])
+    E, O = np.nonzero(par == 0)[0], np.nonzero(par == 1)[0]
+    A = A.tocsr()
+    S = sp.diags(A[E][:, E].diagonal()) - A[E][:, O] @ sp.diags(1.0 / A[O][:, O].diagonal()) @ A[O][:, E]
+    dS = S.diagonal()
+    s = solver(m)
+    rng = np.random.default_rng(4)
+    r = rng.normal(size=lay.n).astype(np.float32)
+    z = s.apply_precond(dev(r), "schur").cpu().numpy().astype(np.float64)
+    assert np.all(z[O] == 0.0)
+    ref = r[E].astype(np.float64) / dS
+    assert np.all(np.abs(z[E] - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-30)
+    u = rng.normal(size=lay.n).astype(np.float32)
+    v = rng.normal(size=lay.n).astype(np.float32)
+    Bu = s.apply_precond(dev(u)).cpu().numpy().astype(np.float64)
+    Bv = s.apply_precond(dev(v)).cpu().numpy().astype(np.float64)
+    Buv = s.apply_precond(dev(u + 2.0 * v)).cpu().numpy().astype(np.float64)
+    assert np.all(Bu[O] == 0.0)
+    uv, vu = float(u.astype(np.float64) @ Bv), float(v.astype(np.float64) @ Bu)
+    scale = float(np.abs(u) @ np.abs(Bv))
+    assert abs(uv - vu) <= 1e-5 * scale
+    assert float(u.astype(np.float64) @ Bu) > 0 and float(v.astype(np.float64) @ Bv) > 0
+    lin = Buv - (Bu + 2.0 * Bv)
+    assert np.abs(lin).max() <= 1e-5 * np.abs(Buv).max()
+    from paper_1807_00410_amd.solver import PnError
+    with pytest.raises(PnError):
+        s.apply_precond(dev(r), 2)  # PN_VARIANT_CG has no such preconditioner
+    s.close()
