@@ -1623,6 +1623,38 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
   return result;
 }
 
+pn_status solve_padded_mg(pn_ctx* c, double tol, const pn_solve_opts& o, pn_solve_info* info) {
+  if (o.variant != PN_VARIANT_SCHUR_MG || o.precision != PN_FP32_IR || !mg_ok(c) || c->use_lds)
+    return fail(c, PN_ERR_ARG, "the padded multigrid solve needs PN_VARIANT_SCHUR_MG, FP32_IR and vacuum boundaries");
+  if (info) std::memset(info, 0, sizeof(*info));
+  const auto t0 = std::chrono::steady_clock::now();
+  pn_status s = solve_impl<float>(c, tol, o, info);
+  PN_HIP(hipStreamSynchronize(c->sstream));
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return s;
+}
+
+bool mg_supported(const pn_ctx* c) { return c && mg_ok(c) && !c->use_lds; }
+
+pn_status borrow_workspace(pn_ctx* c, void* const* v) {
+  float** dst[6] = {&c->r32[0], &c->r32[1], &c->s32, &c->p32, &c->q32, &c->d32};
+  for (int i = 0; i < 6; ++i) *dst[i] = static_cast<float*>(v[i]);
+  if (!c->m16) {
+    PN_HIP(hipMalloc(&c->m16, sizeof(uint16_t) * c->nv));
+    PN_HIP(hipMemsetAsync(c->m16, 0, sizeof(uint16_t) * c->nv, c->sstream));
+  }
+  if (!c->st) PN_HIP(hipMalloc(&c->st, sizeof(DevState)));
+  if (!c->st_host) PN_HIP(hipHostMalloc(&c->st_host, sizeof(DevState), hipHostMallocDefault));
+  if (!c->partials) PN_HIP(hipMalloc(&c->partials, sizeof(double) * 2 * c->max_blocks));
+  PN_HIP(hipStreamSynchronize(c->sstream));
+  return PN_OK;
+}
+
+void unborrow_workspace(pn_ctx* c) {
+  c->r32[0] = c->r32[1] = c->s32 = c->p32 = c->q32 = c->d32 = c->b32 = nullptr;
+  c->x64 = nullptr;
+}
+
 extern "C" pn_status pn_solve(pn_ctx* c, const float* rhs, double* x, double tol, const pn_solve_opts* opts,
                               pn_solve_info* info) {
   if (!c) return PN_ERR_ARG;

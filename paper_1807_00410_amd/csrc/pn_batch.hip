@@ -427,7 +427,14 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
   if (o.max_iter < 1 || o.max_refine < 0 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0))
     return bfail(b, PN_ERR_ARG, "invalid solve options");
   if (o.precision != PN_FP32_IR) return bfail(b, PN_ERR_ARG, "the batched solve runs FP32 with FP64 refinement only");
-  if (o.variant < PN_VARIANT_AUTO || o.variant > PN_VARIANT_CG_EQ) return bfail(b, PN_ERR_ARG, "unknown variant");
+  if (o.variant < PN_VARIANT_AUTO || o.variant > PN_VARIANT_SCHUR_MG || o.variant == PN_VARIANT_SCHUR)
+    return bfail(b, PN_ERR_ARG, "unknown variant");
+  const bool mgpath = o.variant == PN_VARIANT_SCHUR_MG;
+  if (mgpath)
+    for (int p = 0; p < b->nprob; ++p)
+      if (!mg_supported(b->prob[p]))
+        return bfail(b, PN_ERR_ARG, "problem " + std::to_string(p) + ": the multigrid variant needs the vacuum "
+                                    "boundary on every axis and positive extinction");
   const bool cg = o.variant != PN_VARIANT_CGLS;
   const bool eq = o.variant == PN_VARIANT_AUTO || o.variant == PN_VARIANT_CG_EQ;
   if (info) std::memset(info, 0, sizeof(pn_solve_info) * b->nsys);
@@ -457,6 +464,37 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
                          (long)c->nv, 0.0);
       B_HIP(hipGetLastError());
     }
+  }
+  if (mgpath) {
+    // per problem: the first system's scratch vectors serve as the Krylov
+    // workspace; every system is solved by the single-system even-parity
+    // multigrid path on its own Q and iterate (one captured graph per problem)
+    B_HIP(hipStreamSynchronize(ss));
+    pn_status result = PN_OK;
+    int first_bad = -1;
+    for (int p = 0; p < b->nprob; ++p) {
+      pn_ctx* c = b->prob[p];
+      pn_status e = borrow_workspace(c, b->sys_h[p * b->nrhs].vec);
+      if (e != PN_OK) { unborrow_workspace(c); return bfail(b, e, std::string("workspace: ") + pn_last_error(c)); }
+      for (int j = 0; j < b->nrhs; ++j) {
+        const int i = p * b->nrhs + j;
+        c->b32 = static_cast<float*>(b->sys_h[i].vec[BV_B]);
+        c->x64 = static_cast<double*>(b->sys_h[i].vec[BV_X64]);
+        pn_solve_info si;
+        const pn_status s = solve_padded_mg(c, tol, o, &si);
+        if (info) info[i] = si;
+        if (s != PN_OK && first_bad < 0) { first_bad = i; result = s; }
+      }
+      unborrow_workspace(c);
+    }
+    for (int i = 0; i < b->nsys; ++i)
+      B_HIP((launch_pack<double, double, 1>(b->prob[i / b->nrhs], (const double*)b->sys_h[i].vec[BV_X64], x[i], ss)));
+    B_HIP(hipEventRecord(b->ev_out, ss));
+    B_HIP(hipStreamWaitEvent(b->stream, b->ev_out, 0));
+    B_HIP(hipStreamSynchronize(ss));
+    if (first_bad >= 0)
+      bfail(b, result, "system " + std::to_string(first_bad) + ": " + pn_status_string(result));
+    return result;
   }
   const int gi = o.graph_iters < 2 ? 2 : (o.graph_iters + 1) & ~1;  // even: r ends in r0
   {

@@ -193,6 +193,19 @@ int tune_zchunk(pn_ctx* c, const float* x, float* y, int iters, double* best_ms)
 bool tune_lookup(const pn_ctx* c, int* zchunk, double* ms);
 void tune_store(const pn_ctx* c, int zchunk, double ms);
 void free_ctx(pn_ctx* c);
+// The even-parity multigrid solve of the padded Q in c->b32 from the iterate
+// in c->x64 (both set by the caller) on the context's solve stream (the
+// batched solve's PN_VARIANT_SCHUR_MG path); o.variant must be SCHUR_MG.
+pn_status solve_padded_mg(pn_ctx* c, double tol, const pn_solve_opts& o, pn_solve_info* info);
+// True when the multigrid even-parity solve applies to the context.
+bool mg_supported(const pn_ctx* c);
+// Points the FP32 scratch vectors (r0, r1, s, p, q, d) of a context created
+// without workspace at caller-owned padded buffers v[0..5] and allocates the
+// small owned parts (bfloat16 preconditioner, device scalars, partials) on
+// first use; unborrow_workspace sets every borrowed pointer (and b32, x64)
+// back to NULL.
+pn_status borrow_workspace(pn_ctx* c, void* const* v);
+void unborrow_workspace(pn_ctx* c);
 
 inline PackArgs pack_args(const pn_ctx* c) {
   PackArgs p;

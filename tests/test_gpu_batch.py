@@ -212,3 +212,47 @@ def test_batch_problem_context_refuses_workspace_calls():
         assert calls == [L.PN_ERR_ARG] * len(calls)
         assert b"no Krylov workspace" in lib.pn_last_error(ctx)
         torch.cuda.synchronize()
+
+
+def test_batch_multigrid_matches_single_and_oracle():
+    # PN_VARIANT_SCHUR_MG: every system by the single-system multigrid
+    # even-parity solve on its own right-hand side; equals pn_solve bitwise
+    # (same launch shape) and reaches the oracle's answer
+    from paper_1807_00410_amd.solver import Batch, Solver
+    nrhs = 3
+    media = config_batch(seed=9, nmedia=4, nrhs=nrhs, sizes=(8, 11, 16), orders=(1, 3, 5, 7))
+    with Batch(problems(media), nrhs) as B:
+        rhs = [packed_rhs(B.layouts[p], q) for p, m in enumerate(media) for q in m.q00]
+        xs, infos = B.solve(rhs, tol=1e-8, variant="schur_mg")
+        xs2, infos2 = B.solve(rhs, tol=1e-8, variant="schur_mg")  # graphs reused: same result
+        zs = [B.zchunk(p) for p in range(len(media))]
+    for p, m in enumerate(media):
+        A, lay = assemble(m.order, m.dims, m.sigma_t, m.albedo, m.g, m.sigma_t_min, bc=m.bc)
+        s = Solver(m.order, m.dims, dev(m.sigma_t), dev(m.albedo), g=m.g, sigma_t_min=m.sigma_t_min, bc=m.bc)
+        s.set_zchunk(zs[p])
+        for r in range(nrhs):
+            i = p * nrhs + r
+            x1, i1 = s.solve(rhs[i], tol=1e-8, variant="schur_mg")
+            assert infos[i]["status"] == 0 and i1["inner_iters"] == infos[i]["inner_iters"]
+            assert torch.equal(x1, xs[i]) and torch.equal(xs[i], xs2[i])
+            b = rhs_isotropic(lay, m.q00[r])
+            u = oracle_solution(A, b)
+            xv = xs[i].cpu().numpy()
+            res = np.linalg.norm(b - A @ xv) / np.linalg.norm(b)
+            err = np.linalg.norm(xv - u) / np.linalg.norm(u)
+            print("system %d (P%d %s): iters=%d res=%.3g err=%.3g" % (i, m.order, m.dims, infos[i]["inner_iters"],
+                                                                     res, err), flush=True)
+            assert res <= 1.01e-8 and err <= 1e-5
+        s.close()
+
+
+def test_batch_multigrid_refused_with_a_periodic_problem():
+    from paper_1807_00410_amd.solver import Batch, PnError
+    media = [config_small(3, (6, 5, 4), seed=1, sigma_range=(2.0, 20.0), sigma_t_min=1.0),
+             config_small(3, (6, 5, 4), seed=2, sigma_range=(2.0, 20.0), sigma_t_min=1.0, bc=1)]
+    with Batch(problems(media), 1) as B:
+        rhs = [packed_rhs(B.layouts[p], m.q00[0]) for p, m in enumerate(media)]
+        with pytest.raises(PnError):
+            B.solve(rhs, tol=1e-8, variant="schur_mg")
+        xs, infos = B.solve(rhs, tol=1e-8)  # the batched CG path still serves the mixed batch
+        assert all(d["status"] == 0 for d in infos)
