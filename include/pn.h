@@ -441,8 +441,16 @@ long long pn_batch_unknowns(const pn_batch* batch);
 /* Solves every system to ||Q - A x||_2 <= tol ||Q||_2.  rhs and x are HOST
  * arrays of nprob * nrhs DEVICE pointers (packed layout of the system's
  * problem; rhs FP32, x FP64 in/out as for pn_solve).  opts as for pn_solve;
- * precision must be PN_FP32_IR.  info: NULL or a host array of nprob * nrhs
- * entries, one per system (seconds = wall time of the whole batch).  Returns
+ * precision must be PN_FP32_IR.  variant: AUTO (= CG_EQ), CG_EQ, CG or CGLS
+ * run every system of an order in shared launches (one captured graph over
+ * all systems); SCHUR_MG solves the systems one after another by the
+ * single-system multigrid even-parity path (bitwise the result of pn_solve
+ * with the same z-chunk), each problem using its first system's scratch
+ * vectors as the Krylov workspace and keeping its preconditioner and graph
+ * (PN_ERR_ARG unless every problem has the vacuum boundary on every axis and
+ * positive extinction); SCHUR is refused.  info: NULL or a host array of
+ * nprob * nrhs entries, one per system (seconds = wall time of the whole
+ * batch, or of the system's own solve with SCHUR_MG).  Returns
  * PN_OK when every system converged, else the status of the first system that
  * did not (the others are still solved; see info).  Synchronous. */
 pn_status pn_batch_solve(pn_batch* batch, const float* const* rhs, double* const* x, double tol,
