@@ -147,8 +147,9 @@ typedef struct {
  * coefficient's lattice and V one V-cycle on the Galerkin coarse operators
  * (damped Jacobi smoothing, coarsening down to at most 5 points per axis).
  * B is symmetric positive definite and formed per solve from the medium;
- * the solution is the same, only the iteration count changes.  Needs the
- * vacuum boundary on every axis (PN_ERR_ARG otherwise).
+ * the solution is the same, only the iteration count changes.  A periodic
+ * axis is cut at its seam in the preconditioner only (the solve stays
+ * periodic).  PN_ERR_ARG where SCHUR is refused.
  * CGLS: the residual-based CGLS
  * form (r <- r - alpha q fused into s = A^T r).  CG: CG on the normal
  * equations A^T A u = A^T Q with the recursive normal residual
@@ -159,10 +160,9 @@ typedef struct {
  * every transport neighbour present, formed from the medium inside the
  * kernels: no extra memory traffic); the inner stop then tests the W-weighted
  * residual.  Needs the register-window stencil (PN_ERR_ARG with pn_set_tiles
- * or PN_FP64).  AUTO: SCHUR_MG on the register-window stencil when every axis
- * is vacuum, else SCHUR (CG_EQ when an axis is Neumann or some cell has zero
- * extinction), CG on the LDS-tiled one; the batched solve treats AUTO as
- * CG_EQ.  The FP64 refinement checks the true, unweighted residual
+ * or PN_FP64).  AUTO: SCHUR_MG on the register-window stencil (CG_EQ when an
+ * axis is Neumann or some cell has zero extinction), CG on the LDS-tiled one;
+ * the batched solve treats AUTO as CG_EQ.  The FP64 refinement checks the true, unweighted residual
  * ||Q - A x|| in every case. */
 #define PN_VARIANT_AUTO 0
 #define PN_VARIANT_CGLS 1
@@ -249,12 +249,11 @@ pn_status pn_apply_schur(pn_ctx* ctx, const float* x, float* y);
 /* The preconditioner of the even-parity solve applied to r: z_e = B r_e on
  * the even-band entries, z_o = 0.  variant PN_VARIANT_SCHUR: B = M, the
  * Jacobi inverse diagonal of S (bfloat16); PN_VARIANT_SCHUR_MG: B = 0.6 M +
- * P V P^T, the multigrid form (see the variants below; vacuum boundary on
- * every axis).  B is symmetric positive definite and depends on the medium
+ * P V P^T, the multigrid form (see the variants below).  B is symmetric positive definite and depends on the medium
  * only; it is formed at the first call (or solve) and kept.  r, z: device
  * FP32 packed vectors (n_unknowns), not overlapping.  Overwrites the Krylov
  * workspace (a following pn_solve re-initialises it).  PN_ERR_ARG for another
- * variant, a Neumann axis, zero extinction, or (MG) a non-vacuum axis.
+ * variant, a Neumann axis or zero extinction.
  * Asynchronous on the context stream. */
 pn_status pn_apply_precond(pn_ctx* ctx, int variant, const float* r, float* z);
 
@@ -342,8 +341,8 @@ pn_status pn_bench_apply(pn_ctx* ctx, int iters, int transpose, double* ms_per_a
  *   PN_KERNEL_EVEN_R     r_e -= alpha (D_e p_e + T_eo w_o) (even rows) with
  *                        <r, M r>, <r, r>
  *   PN_KERNEL_PCG_XP     x += alpha p, p = M r + beta p
- * and of its multigrid form (PN_VARIANT_SCHUR_MG; vacuum boundary on every
- * axis, PN_ERR_ARG otherwise), inside odd rows | even rows | V-cycle | x/p:
+ * and of its multigrid form (PN_VARIANT_SCHUR_MG; PN_ERR_ARG where it does
+ * not apply), inside odd rows | even rows | V-cycle | x/p:
  *   PN_KERNEL_MG_VCYCLE  the whole V-cycle on P^T r (restriction, down and up
  *                        passes of every level, coarsest solve), timed as one
  *   PN_KERNEL_PCG_XP_MG  x += alpha p, p = omega_f M r + P z_1 + beta p */
@@ -447,8 +446,8 @@ long long pn_batch_unknowns(const pn_batch* batch);
  * single-system multigrid even-parity path (bitwise the result of pn_solve
  * with the same z-chunk), each problem using its first system's scratch
  * vectors as the Krylov workspace and keeping its preconditioner and graph
- * (PN_ERR_ARG unless every problem has the vacuum boundary on every axis and
- * positive extinction); SCHUR is refused.  info: NULL or a host array of
+ * (PN_ERR_ARG when some problem has a Neumann axis or zero extinction);
+ * SCHUR is refused.  info: NULL or a host array of
  * nprob * nrhs entries, one per system (seconds = wall time of the whole
  * batch, or of the system's own solve with SCHUR_MG).  Returns
  * PN_OK when every system converged, else the status of the first system that

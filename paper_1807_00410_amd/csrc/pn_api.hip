@@ -680,7 +680,7 @@ extern "C" pn_status pn_apply_precond(pn_ctx* c, int variant, const float* r, fl
     return fail(c, PN_ERR_ARG, "variant must be PN_VARIANT_SCHUR or PN_VARIANT_SCHUR_MG");
   const bool mg = variant == PN_VARIANT_SCHUR_MG;
   if (!schur_ok(c)) return fail(c, PN_ERR_ARG, "the even-parity preconditioner needs no Neumann axis and positive extinction");
-  if (mg && !mg_ok(c)) return fail(c, PN_ERR_ARG, "the multigrid preconditioner needs the vacuum boundary on every axis");
+  if (mg && !mg_ok(c)) return fail(c, PN_ERR_ARG, "the multigrid preconditioner needs no Neumann axis and positive extinction");
   const int need = mg ? 3 : 1;
   if ((c->prec_ready & need) != need) {
     pn_status e = schur_prepare(c, mg, c->stream);
@@ -783,7 +783,7 @@ extern "C" pn_status pn_bench_kernel(pn_ctx* c, int kernel, int iters, double* m
     return fail(c, PN_ERR_ARG, "the in-loop kernels are timed on the register-window stencil");
   const bool mgk = kernel >= PN_KERNEL_MG_VCYCLE;
   if (mgk) {
-    if (!mg_ok(c)) return fail(c, PN_ERR_ARG, "the multigrid kernels need the vacuum boundary on every axis");
+    if (!mg_ok(c)) return fail(c, PN_ERR_ARG, "the multigrid kernels need no Neumann axis and positive extinction");
     pn_status e = schur_prepare(c, true, c->stream);  // Jacobi diagonal and multigrid operators
     if (e != PN_OK) return e;
   }
@@ -1003,16 +1003,16 @@ static bool schur_ok(const pn_ctx* c) {
 }
 
 // ------------------------------------------------ multigrid preconditioner --
-// B r = omega_f M r + P V(P^T r) (see pn_mg.h), on contexts with the vacuum
-// boundary on every axis (aggregation over the class extents).
+// B r = omega_f M r + P V(P^T r) (see pn_mg.h).  Aggregation runs over the
+// class extents; a periodic axis is cut at its seam in the preconditioner
+// (the padded halo the coarse operators are formed from holds zeros there, so
+// the seam faces' weights stay on the diagonal: B remains symmetric positive
+// definite, only less accurate next to the seam).
 constexpr float kMgOmega = 0.9f;      // damped Jacobi on the coarse levels
 constexpr int kMgSweeps = 16;         // damped Jacobi sweeps on the coarsest level
 constexpr int kMgCoarsest = 5;        // coarsen until every axis has at most this many points
 
-static bool mg_ok(const pn_ctx* c) {
-  return schur_ok(c) && c->bcs[0] == BC_VACUUM && c->bcs[1] == BC_VACUUM && c->bcs[2] == BC_VACUUM &&
-         c->even.nk >= 1 && c->even.nk <= kMgMaxEven;
-}
+static bool mg_ok(const pn_ctx* c) { return schur_ok(c) && c->even.nk >= 1 && c->even.nk <= kMgMaxEven; }
 
 static long long mg_points(const MgGeom& g, int s) { return (long long)g.ext[s][0] * g.ext[s][1] * g.ext[s][2]; }
 
@@ -1418,7 +1418,7 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
   // ping-pong, the A^T pass streams two).
   // FP32 even-parity PCG (Schur complement): SCHUR, and AUTO on the
   // register-window stencil when no axis is Neumann
-  // with the multigrid preconditioner: SCHUR_MG, and AUTO when every axis is vacuum
+  // with the multigrid preconditioner: SCHUR_MG, and AUTO whenever the even-parity form applies
   const bool mg = (sizeof(T) == 4) && mg_ok(c) && !c->use_lds &&
                   (o.variant == PN_VARIANT_SCHUR_MG || o.variant == PN_VARIANT_AUTO);
   const bool schur = (sizeof(T) == 4) && schur_ok(c) &&
@@ -1625,7 +1625,7 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
 
 pn_status solve_padded_mg(pn_ctx* c, double tol, const pn_solve_opts& o, pn_solve_info* info) {
   if (o.variant != PN_VARIANT_SCHUR_MG || o.precision != PN_FP32_IR || !mg_ok(c) || c->use_lds)
-    return fail(c, PN_ERR_ARG, "the padded multigrid solve needs PN_VARIANT_SCHUR_MG, FP32_IR and vacuum boundaries");
+    return fail(c, PN_ERR_ARG, "the padded multigrid solve needs PN_VARIANT_SCHUR_MG, FP32_IR and no Neumann axis");
   if (info) std::memset(info, 0, sizeof(*info));
   const auto t0 = std::chrono::steady_clock::now();
   pn_status s = solve_impl<float>(c, tol, o, info);
@@ -1673,8 +1673,8 @@ extern "C" pn_status pn_solve(pn_ctx* c, const float* rhs, double* x, double tol
   if (o.variant == PN_VARIANT_SCHUR && (!schur_ok(c) || o.precision != PN_FP32_IR))
     return fail(c, PN_ERR_ARG, "the even-parity Schur variant needs FP32_IR, no Neumann axis and positive extinction");
   if (o.variant == PN_VARIANT_SCHUR_MG && (!mg_ok(c) || c->use_lds || o.precision != PN_FP32_IR))
-    return fail(c, PN_ERR_ARG, "the multigrid even-parity variant needs FP32_IR, the register-window stencil, the "
-                               "vacuum boundary on every axis and positive extinction");
+    return fail(c, PN_ERR_ARG, "the multigrid even-parity variant needs FP32_IR, the register-window stencil, no "
+                               "Neumann axis and positive extinction");
   if (o.variant == PN_VARIANT_CG_EQ && (c->use_lds || o.precision != PN_FP32_IR))
     return fail(c, PN_ERR_ARG, "the equilibrated CG variant needs FP32_IR and the register-window stencil");
   if (info) std::memset(info, 0, sizeof(*info));

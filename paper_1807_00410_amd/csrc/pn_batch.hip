@@ -433,8 +433,8 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
   if (mgpath)
     for (int p = 0; p < b->nprob; ++p)
       if (!mg_supported(b->prob[p]))
-        return bfail(b, PN_ERR_ARG, "problem " + std::to_string(p) + ": the multigrid variant needs the vacuum "
-                                    "boundary on every axis and positive extinction");
+        return bfail(b, PN_ERR_ARG, "problem " + std::to_string(p) + ": the multigrid variant needs no Neumann "
+                                    "axis and positive extinction");
   const bool cg = o.variant != PN_VARIANT_CGLS;
   const bool eq = o.variant == PN_VARIANT_AUTO || o.variant == PN_VARIANT_CG_EQ;
   if (info) std::memset(info, 0, sizeof(pn_solve_info) * b->nsys);

@@ -246,10 +246,10 @@ def test_batch_multigrid_matches_single_and_oracle():
         s.close()
 
 
-def test_batch_multigrid_refused_with_a_periodic_problem():
+def test_batch_multigrid_refused_with_a_neumann_problem():
     from paper_1807_00410_amd.solver import Batch, PnError
     media = [config_small(3, (6, 5, 4), seed=1, sigma_range=(2.0, 20.0), sigma_t_min=1.0),
-             config_small(3, (6, 5, 4), seed=2, sigma_range=(2.0, 20.0), sigma_t_min=1.0, bc=1)]
+             config_small(3, (6, 5, 4), seed=2, sigma_range=(2.0, 20.0), sigma_t_min=1.0, bc=2)]
     with Batch(problems(media), 1) as B:
         rhs = [packed_rhs(B.layouts[p], m.q00[0]) for p, m in enumerate(media)]
         with pytest.raises(PnError):

@@ -332,12 +332,12 @@ def test_solve_equilibrated_cg_variant(order, n, bc):
     i_eq = _solve_and_check(m, 1e-8, "fp32_ir", variant="cg_eq")
     i_plain = _solve_and_check(m, 1e-8, "fp32_ir", variant="cg")
     print("iterations: equilibrated %d, plain %d" % (i_eq["inner_iters"], i_plain["inner_iters"]))
-    # AUTO is the even-parity Schur form on the register-window stencil, with
-    # the multigrid preconditioner when every axis is vacuum
+    # AUTO is the even-parity Schur form with the multigrid preconditioner on
+    # the register-window stencil
     s = make_solver(m)
     rhs = s.rhs_from_q00(dev(m.q00[0]))
     xa, ia = s.solve(rhs, tol=1e-8)
-    xe, ie = s.solve(rhs, tol=1e-8, variant="schur_mg" if bc == 0 else "schur")
+    xe, ie = s.solve(rhs, tol=1e-8, variant="schur_mg")
     assert ia["inner_iters"] == ie["inner_iters"] and torch.equal(xa, xe)
     s.close()
 
