@@ -52,9 +52,15 @@ Dims mk(int B, int nx, int ny, int nz) {
 Dims half(const Dims& d) { return mk(d.B, d.W / 2, d.H / 2, d.D / 2); }
 
 // --- launches shared by the primitives and the network ---
+// persistent convolution blocks: every CU holds two (55 KB of LDS each)
+int conv_blocks(const Dims& d) {
+  const long long groups = (d.V + 255) / 256;  // 4 waves x 2 tiles x 32 voxels
+  return (int)(groups < 512 ? (groups < 1 ? 1 : groups) : 512);
+}
+
 hipError_t conv_fwd(const Dims& d, const uint16_t* x, const uint16_t* w, const float* bias, bool relu, bool f32,
                     void* y, hipStream_t s) {
-  const int nb = (int)((d.V + 255) / 256);  // 4 waves x 2 tiles x 32 voxels
+  const int nb = conv_blocks(d);
   if (f32) {
     if (relu) hipLaunchKernelGGL((k_conv3d<false, true, true>), dim3(nb), dim3(kNB), 0, s, x, w, bias, y, d);
     else hipLaunchKernelGGL((k_conv3d<false, false, true>), dim3(nb), dim3(kNB), 0, s, x, w, bias, y, d);
@@ -66,7 +72,7 @@ hipError_t conv_fwd(const Dims& d, const uint16_t* x, const uint16_t* w, const f
 }
 
 hipError_t conv_dgrad(const Dims& d, const uint16_t* g, const uint16_t* w, uint16_t* dx, hipStream_t s) {
-  const int nb = (int)((d.V + 255) / 256);
+  const int nb = conv_blocks(d);
   hipLaunchKernelGGL((k_conv3d<true, false, false>), dim3(nb), dim3(kNB), 0, s, g, w, (const float*)nullptr,
                      (void*)dx, d);
   return hipGetLastError();

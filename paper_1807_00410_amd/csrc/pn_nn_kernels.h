@@ -10,7 +10,10 @@
 // accumulated over the 27 taps in FP32 with v_mfma_f32_32x32x16_bf16 (M = 32
 // voxels, N = 32 output channels, K = 16 input channels per instruction).  A
 // wave owns two 32-voxel tiles so every weight fragment read from LDS feeds
-// two MFMAs; the block stages the 55 KB weight tensor in LDS once.
+// two MFMAs; the blocks are persistent (two per CU, the LDS bound) and stage
+// the 55 KB weight tensor in LDS once, then loop over voxel tiles; the tap
+// loop is unrolled by three (four tiles per wave, or all 27 taps unrolled --
+// 256 VGPRs, one wave per SIMD -- were measured slower).
 // The input gradient is the same kernel on the flipped, transposed weights
 // (the flip is done while filling LDS).  The weight gradient contracts over
 // voxels: D[co][ci] = sum_v g[v][co] x[v + d_t][ci], again on MFMA with K = 16
@@ -75,67 +78,76 @@ __global__ void __launch_bounds__(kNB) k_conv3d(const uint16_t* __restrict__ X, 
     const uint4* src = reinterpret_cast<const uint4*>(Wg);
     for (int i = threadIdx.x; i < kWElems / 8; i += kNB) lw4[i] = src[i];
   } else {
+    // n (= ci of w) fastest over the threads: the reads of w are contiguous
     for (int i = threadIdx.x; i < kWElems; i += kNB) {
-      const int t = i / (kC * kC), n = (i / kC) % kC, k = i % kC;  // n: output = ci of w, k: input = co of w
-      lw[i] = Wg[((kTaps - 1 - t) * kC + k) * kC + n];
+      const int t = i / (kC * kC), k = (i / kC) % kC, n = i % kC;  // n: output = ci of w, k: input = co of w
+      lw[(t * kC + n) * kC + k] = Wg[((kTaps - 1 - t) * kC + k) * kC + n];
     }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 31, half = lane >> 5;
-  const long long tile0 = ((long long)blockIdx.x * (kNB / 64) + wv) * kMT;
   const long long HW = (long long)d.H * d.W;
-  int zz[kMT], yy[kMT], xx[kMT];
-  long long vv[kMT];
-#pragma unroll
-  for (int m = 0; m < kMT; ++m) {
-    vv[m] = (tile0 + m) * 32 + row;
-    int b;
-    if (vv[m] < d.V) {
-      decompose(vv[m], d, b, zz[m], yy[m], xx[m]);
-    } else {
-      zz[m] = -4; yy[m] = 0; xx[m] = 0;  // fails every bounds test
-    }
-  }
-  f32x16 acc[kMT];
-#pragma unroll
-  for (int m = 0; m < kMT; ++m)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[m][r] = 0.f;
-
-  for (int t = 0; t < kTaps; ++t) {
-    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-    const long long doff = dz * HW + (long long)dy * d.W + dx;
-    bool ok[kMT];
-    const uint4* src[kMT];
+  const float bj = bias ? bias[row] : 0.f;
+  // persistent blocks: the weights are staged once, then groups of
+  // (4 waves x kMT tiles x 32 voxels) are taken in turn
+  const long long ngroups = (d.V + 32 * kMT * (kNB / 64) - 1) / (32 * kMT * (kNB / 64));
+  for (long long grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const long long tile0 = (grp * (kNB / 64) + wv) * kMT;
+    int zz[kMT], yy[kMT], xx[kMT];
+    long long vv[kMT];
 #pragma unroll
     for (int m = 0; m < kMT; ++m) {
-      ok[m] = (unsigned)(zz[m] + dz) < (unsigned)d.D && (unsigned)(yy[m] + dy) < (unsigned)d.H &&
-              (unsigned)(xx[m] + dx) < (unsigned)d.W;
-      src[m] = reinterpret_cast<const uint4*>(X + (ok[m] ? (vv[m] + doff) * kC : 0) + half * 8);
-    }
-#pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
-      const uint4 bw = lw4[((t * kC + row) * kC + kh * 16 + half * 8) / 8];
-#pragma unroll
-      for (int m = 0; m < kMT; ++m) {
-        const uint4 av = ok[m] ? src[m][kh * 2] : make_uint4(0, 0, 0, 0);
-        acc[m] = mfma(as_bf8(av), as_bf8(bw), acc[m]);
+      vv[m] = (tile0 + m) * 32 + row;
+      int b;
+      if (vv[m] < d.V) {
+        decompose(vv[m], d, b, zz[m], yy[m], xx[m]);
+      } else {
+        zz[m] = -4; yy[m] = 0; xx[m] = 0;  // fails every bounds test
       }
     }
-  }
-  // D[i][j]: j = row (output channel), i = 8 (r / 4) + 4 half + r % 4 (voxel in tile)
-  const float bj = bias ? bias[row] : 0.f;
+    f32x16 acc[kMT];
 #pragma unroll
-  for (int m = 0; m < kMT; ++m) {
+    for (int m = 0; m < kMT; ++m)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const long long v = (tile0 + m) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-      if (v < d.V) {
-        float o = acc[m][r] + bj;
-        if (RELU) o = fmaxf(o, 0.f);
-        if constexpr (OUTF32) static_cast<float*>(Yv)[v * kC + row] = o;
-        else static_cast<uint16_t*>(Yv)[v * kC + row] = f2bf(o);
+      for (int r = 0; r < 16; ++r) acc[m][r] = 0.f;
+
+    // taps unrolled by three (one x row of the stencil): the loads of a row
+    // are issued ahead of its matrix instructions at two waves per SIMD
+#pragma unroll 3
+    for (int t = 0; t < kTaps; ++t) {
+      const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      const long long doff = dz * HW + (long long)dy * d.W + dx;
+      bool ok[kMT];
+      const uint4* src[kMT];
+#pragma unroll
+      for (int m = 0; m < kMT; ++m) {
+        ok[m] = (unsigned)(zz[m] + dz) < (unsigned)d.D && (unsigned)(yy[m] + dy) < (unsigned)d.H &&
+                (unsigned)(xx[m] + dx) < (unsigned)d.W;
+        src[m] = reinterpret_cast<const uint4*>(X + (ok[m] ? (vv[m] + doff) * kC : 0) + half * 8);
+      }
+#pragma unroll
+      for (int kh = 0; kh < 2; ++kh) {
+        const uint4 bw = lw4[((t * kC + row) * kC + kh * 16 + half * 8) / 8];
+#pragma unroll
+        for (int m = 0; m < kMT; ++m) {
+          const uint4 av = ok[m] ? src[m][kh * 2] : make_uint4(0, 0, 0, 0);
+          acc[m] = mfma(as_bf8(av), as_bf8(bw), acc[m]);
+        }
+      }
+    }
+    // D[i][j]: j = row (output channel), i = 8 (r / 4) + 4 half + r % 4 (voxel in tile)
+#pragma unroll
+    for (int m = 0; m < kMT; ++m) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long long v = (tile0 + m) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        if (v < d.V) {
+          float o = acc[m][r] + bj;
+          if (RELU) o = fmaxf(o, 0.f);
+          if constexpr (OUTF32) static_cast<float*>(Yv)[v * kC + row] = o;
+          else static_cast<uint16_t*>(Yv)[v * kC + row] = f2bf(o);
+        }
       }
     }
   }
