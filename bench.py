@@ -547,6 +547,39 @@ def counters_summary(args):
             fh.write("\n".join(sl) + "\n")
 
 
+def net_kernels(args):
+    """--net-kernels: the U-Net's 3x3x3 32 -> 32 convolution (forward with
+    ReLU, input gradient, weight gradient) at the U-Net's level sizes for a
+    batch of 4 64^3 volumes, each timed over 20 launches with HIP events on
+    the current stream; 55,296 flop per voxel against the 2.5 PFLOP/s dense
+    BF16 peak."""
+    import torch
+    from paper_1807_00410_amd import net as N
+    torch.manual_seed(0)
+    rows = []
+    for n in (64, 32, 16, 8):
+        x = (torch.randn(4, n, n, n, 32, device="cuda") * 0.5).to(torch.bfloat16)
+        g = (torch.randn(4, n, n, n, 32, device="cuda") * 0.5).to(torch.bfloat16)
+        w = (torch.randn(27, 32, 32, device="cuda") * 0.05).to(torch.bfloat16)
+        b = torch.zeros(32, device="cuda")
+        for name, fn in (("forward", lambda: N.conv3d(x, w, b, relu=True)), ("input gradient", lambda: N.conv3d_dgrad(g, w)),
+                         ("weight gradient", lambda: N.conv3d_wgrad(x, g))):  # the API call: with its temporary partials buffer
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 20
+            tf = 55296.0 * 4 * n ** 3 / ms / 1e9
+            rows.append({"kernel": name, "voxels": 4 * n ** 3, "ms": ms, "TFLOPs": tf, "frac": tf / 2500.0})
+            print("%-15s 4 x %2d^3  %.4f ms  %6.0f TFLOP/s  %.3f of peak" % (name, n, ms, tf, tf / 2500.0), flush=True)
+    print(json.dumps({"net_kernels": rows}), flush=True)
+
+
 def profile_solve(args):
     """Profiling mode for rocprofv3 (--profile-solve): the headline workload
     (P5 nebula) solved by the default solver once untimed, then
@@ -635,6 +668,8 @@ def main():
                          "apply_eq, supd, update) "
                          "run in their in-loop form for rocprofv3, then the counter-calibration copies")
     ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--net-kernels", action="store_true",
+                    help="time the U-Net convolution kernels (forward, input and weight gradient) per level")
     ap.add_argument("--counters-summary", default=None, metavar="DIR",
                     help="write profiles/krylov_p5_128_counters.{json,md} from the rocprofv3 outputs in DIR")
     ap.add_argument("--profile-solve", action="store_true",
@@ -656,6 +691,9 @@ def main():
         return
     if args.counters_summary:
         counters_summary(args)
+        return
+    if args.net_kernels:
+        net_kernels(args)
         return
     if args.accuracy:
         accuracy_check(args)

@@ -72,7 +72,7 @@ def generate(n=64, nmedia=250, nrhs=8, seed0=1000, chunk=16, tol=1e-5, workers=1
                         b[lay.offset[0]:lay.offset[1]] = _dev(q).reshape(-1)
                         rhs.append(b)
                 ts = time.time()
-                xs, infos = B.solve(rhs, tol=tol, raise_on_fail=False)
+                xs, infos = B.solve(rhs, tol=tol, raise_on_fail=False, variant="schur_mg")
                 solve_s += time.time() - ts
                 for i, d in enumerate(infos):
                     if d["status"] != 0:
