@@ -180,7 +180,9 @@ static void free_all(pn_ctx* c) {
   if (c->gexec_mg) hipGraphExecDestroy(c->gexec_mg);
   hipFree(c->mg_terms);
   hipFree(c->mg_partials);
-  for (int L = 0; L < kMgMaxLevels; ++L) { hipFree(c->mg_op[L]); hipFree(c->mg_r[L]); hipFree(c->mg_z[L]); hipFree(c->mg_zt[L]); }
+  for (int L = 0; L < kMgMaxLevels; ++L) {
+    hipFree(c->mg_op[L]); hipFree(c->mg_r[L]); hipFree(c->mg_z[L]); hipFree(c->mg_zt[L]); hipFree(c->mg_idg[L]);
+  }
   hipFree(c->med); hipFree(c->med32);
   for (int i = 0; i < 2; ++i) { hipFree(c->r32[i]); hipFree(c->r64[i]); }
   hipFree(c->m16);
@@ -1081,6 +1083,7 @@ static pn_status mg_alloc(pn_ctx* c) {
     PN_HIP(hipMalloc(&c->mg_r[L], sizeof(float) * n));
     PN_HIP(hipMalloc(&c->mg_z[L], sizeof(float) * n));
     PN_HIP(hipMalloc(&c->mg_zt[L], sizeof(float) * n));
+    PN_HIP(hipMalloc(&c->mg_idg[L], sizeof(float) * n));
   }
   c->mg_npart = levels == 1 ? 1 : mg_blocks(g[1]) * f.nk;
   PN_HIP(hipMalloc(&c->mg_partials, sizeof(double) * 2 * c->mg_npart));
@@ -1093,11 +1096,12 @@ static pn_status mg_alloc(pn_ctx* c) {
 static pn_status mg_setup_ops(pn_ctx* c, const float* m32, const float* invdo, hipStream_t st) {
   const MgGeom* g = c->mg_geom;
   hipLaunchKernelGGL(k_mg_setup1, dim3(mg_blocks(g[1]), g[1].nk), dim3(kBlock), 0, st, c->mg_fine, g[1],
-                     (const MgTerms*)c->mg_terms, m32, invdo, c->h > 0.0 ? 1.0 / (c->h * c->h) : 0.0, c->mg_op[1]);
+                     (const MgTerms*)c->mg_terms, m32, invdo, c->h > 0.0 ? 1.0 / (c->h * c->h) : 0.0, c->mg_op[1],
+                     c->mg_idg[1]);
   PN_HIP(hipGetLastError());
   for (int L = 1; L < c->mg_levels; ++L) {
     hipLaunchKernelGGL(k_mg_coarsen, dim3(mg_blocks(g[L + 1]), g[L + 1].nk), dim3(kBlock), 0, st, g[L], g[L + 1],
-                       (const float4*)c->mg_op[L], c->mg_op[L + 1]);
+                       (const float4*)c->mg_op[L], c->mg_op[L + 1], c->mg_idg[L + 1]);
     PN_HIP(hipGetLastError());
   }
   return PN_OK;
@@ -1147,11 +1151,11 @@ static hipError_t mg_vcycle(pn_ctx* c, const float* r, hipStream_t st) {
   const int Lc = c->mg_levels;
   const DevState* ds = c->st;
   hipLaunchKernelGGL(k_mg_restrict0, dim3(mg_blocks(g[1]), g[1].nk), dim3(kBlock), 0, st, c->mg_fine, g[1], r,
-                     (const float4*)c->mg_op[1], c->mg_r[1], c->mg_z[1], kMgOmega, ds);
+                     (const float*)c->mg_idg[1], c->mg_r[1], c->mg_z[1], kMgOmega, ds);
   for (int L = 1; L < Lc; ++L)
     hipLaunchKernelGGL(k_mg_down, mg_tiles(g[L], g[L + 1]), dim3(kBlock), 0, st, g[L], g[L + 1],
                        (const float4*)c->mg_op[L], (const float*)c->mg_r[L], (const float*)c->mg_z[L],
-                       (const float4*)c->mg_op[L + 1], c->mg_r[L + 1], c->mg_z[L + 1], kMgOmega, ds);
+                       (const float*)c->mg_idg[L + 1], c->mg_r[L + 1], c->mg_z[L + 1], kMgOmega, ds);
   hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(kFinBlock), 0, st, g[Lc], (const float4*)c->mg_op[Lc],
                      (const float*)c->mg_r[Lc], c->mg_z[Lc], kMgSweeps, kMgOmega,
                      Lc == 1 ? c->mg_partials : (double*)nullptr, ds);
@@ -1163,7 +1167,7 @@ static hipError_t mg_vcycle(pn_ctx* c, const float* r, hipStream_t st) {
 }
 
 // Even-parity PCG iteration with the multigrid preconditioner: w_o | alpha |
-// r update (<r, M r>, <r, r>) | stop test | V-cycle | beta | x, p.
+// r update (<r, M r>, <r, r> partials) | V-cycle | scalars (stop test, beta) | x, p.
 static hipError_t enqueue_iteration_mg(pn_ctx* c, hipStream_t st) {
   StencilArgs a = base_args(c);
   a.st = c->st;
@@ -1176,12 +1180,10 @@ static hipError_t enqueue_iteration_mg(pn_ctx* c, hipStream_t st) {
   a.x = c->p32; a.y = c->r32[1]; a.m16 = c->m16;
   e = launch_stencil<float, M_EVEN_SR, float>(c, a, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fin_rz_mg<false>, dim3(1), dim3(kFinBlock), 0, st, c->st, (const double*)c->partials,
-                     c->nblocks, 0.0);
   e = mg_vcycle(c, c->r32[1], st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fin_beta_mg<false>, dim3(1), dim3(kFinBlock), 0, st, c->st, (const double*)c->mg_partials,
-                     c->mg_npart, (double)kMgOmegaFine);
+  hipLaunchKernelGGL(k_fin_iter_mg, dim3(1), dim3(kFinBlock), 0, st, c->st, (const double*)c->partials, c->nblocks,
+                     (const double*)c->mg_partials, c->mg_npart, (double)kMgOmegaFine);
   const dim3 vg(pcg_vec_blocks(c), c->even.nk);
   hipLaunchKernelGGL(k_pcg_vec_mg<2>, vg, dim3(kBlock), 0, st, c->d32, (const float*)c->r32[1], c->p32,
                      (const uint16_t*)c->m16, c->mg_fine, c->mg_geom[1], mg_final(c, 1), kMgOmegaFine,

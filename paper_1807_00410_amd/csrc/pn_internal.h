@@ -103,6 +103,7 @@ struct pn_ctx {
   float* mg_r[kMgMaxLevels] = {};
   float* mg_z[kMgMaxLevels] = {};
   float* mg_zt[kMgMaxLevels] = {};
+  float* mg_idg[kMgMaxLevels] = {};  // 1 / diag per level (the same reciprocal every Jacobi step uses)
   double* mg_partials = nullptr;
   int mg_npart = 0;  // block partial pairs of <P^T r, V(P^T r)>
   int prec_ready = 0;  // bit 0: m16 formed, bit 1: the multigrid operators formed

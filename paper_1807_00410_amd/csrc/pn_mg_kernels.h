@@ -45,7 +45,7 @@ static __global__ void __launch_bounds__(kBlock) k_mg_setup1(const MgFine f, con
                                                              const MgTerms* __restrict__ t,
                                                              const float* __restrict__ m32,
                                                              const float* __restrict__ invdo, double invh2,
-                                                             float4* __restrict__ op) {
+                                                             float4* __restrict__ op, float* __restrict__ idg) {
   const int s = blockIdx.y;
   const int n = mg_points(g1, s);
   const int fe[3] = {f.ext[s][0], f.ext[s][1], f.ext[s][2]};
@@ -77,13 +77,14 @@ static __global__ void __launch_bounds__(kBlock) k_mg_setup1(const MgFine f, con
     const double off = wp[0] + wp[1] + wp[2] + wm[0] + wm[1] + wm[2];
     diag = fmax(diag, (1.0 + 1e-6) * off);
     op[g1.off[s] + i] = make_float4((float)diag, (float)wp[0], (float)wp[1], (float)wp[2]);
+    idg[g1.off[s] + i] = mg_rcp((float)diag);
   }
 }
 
 // Galerkin coarsening of an explicit level (aggregates of 2 x 2 x 2).
 static __global__ void __launch_bounds__(kBlock) k_mg_coarsen(const MgGeom gf, const MgGeom gc,
                                                               const float4* __restrict__ opf,
-                                                              float4* __restrict__ opc) {
+                                                              float4* __restrict__ opc, float* __restrict__ idgc) {
   const int s = blockIdx.y;
   const int n = mg_points(gc, s);
   const int fe[3] = {gf.ext[s][0], gf.ext[s][1], gf.ext[s][2]};
@@ -113,6 +114,7 @@ static __global__ void __launch_bounds__(kBlock) k_mg_coarsen(const MgGeom gf, c
     const double off = wp[0] + wp[1] + wp[2] + wm[0] + wm[1] + wm[2];
     diag = fmax(diag, (1.0 + 1e-6) * off);
     opc[gc.off[s] + i] = make_float4((float)diag, (float)wp[0], (float)wp[1], (float)wp[2]);
+    idgc[gc.off[s] + i] = mg_rcp((float)diag);
   }
 }
 
@@ -123,7 +125,7 @@ static __global__ void __launch_bounds__(kBlock) k_mg_coarsen(const MgGeom gf, c
 // columns read this layout in 64-byte pieces and were measured 2x slower).
 static __global__ void __launch_bounds__(kBlock) k_mg_restrict0(const MgFine f, const MgGeom g1,
                                                                 const float* __restrict__ r,
-                                                                const float4* __restrict__ op1,
+                                                                const float* __restrict__ idg1,
                                                                 float* __restrict__ r1, float* __restrict__ z1,
                                                                 float omega, const DevState* __restrict__ st) {
   if (st->stop) return;
@@ -143,7 +145,7 @@ static __global__ void __launch_bounds__(kBlock) k_mg_restrict0(const MgFine f, 
     }
     const long long j = g1.off[s] + i;
     r1[j] = acc;
-    z1[j] = omega * acc * mg_rcp(op1[j].x);
+    z1[j] = omega * acc * idg1[j];
   }
 }
 
@@ -181,7 +183,7 @@ __device__ __forceinline__ float mg_quad_sum(float v) {
 static __global__ void __launch_bounds__(kBlock) k_mg_down(const MgGeom gf, const MgGeom gc,
                                                            const float4* __restrict__ op, const float* __restrict__ r,
                                                            const float* __restrict__ zl,
-                                                           const float4* __restrict__ opc, float* __restrict__ rc,
+                                                           const float* __restrict__ idgc, float* __restrict__ rc,
                                                            float* __restrict__ zc, float omega,
                                                            const DevState* __restrict__ st) {
   if (st->stop) return;
@@ -204,7 +206,7 @@ static __global__ void __launch_bounds__(kBlock) k_mg_down(const MgGeom gf, cons
   if (!(x & 1) && !(y & 1) && X < gc.ext[s][0] && Y < gc.ext[s][1] && Z < gc.ext[s][2]) {
     const long long jc = mg_at(gc, s, X, Y, Z);
     rc[jc] = acc;
-    zc[jc] = omega * acc * mg_rcp(opc[jc].x);
+    zc[jc] = omega * acc * idgc[jc];
   }
 }
 
@@ -352,6 +354,38 @@ __global__ void __launch_bounds__(kFinBlock) k_fin_rz_mg(DevState* st, const dou
       st->iters += 1;
       if (!finite_d(rr) || !finite_d(rz)) { st->breakdown = 1; st->stop = 1; st->nonfinite = 1.0; }
       if (rr <= st->tol2 || st->iters >= st->max_iters || !(rz > 0.0)) st->stop = 1;
+    }
+  }
+}
+
+// One iteration's scalars after the V-cycle: <r, M r> and <r, r> from the
+// even-row pass's partials (pr, nr pairs), <P^T r, V(P^T r)> from the
+// V-cycle's (pc, nc); the stop test on <r, r>, then gamma' = <r, B r> =
+// omega_f <r, M r> + <P^T r, V(P^T r)> and beta = gamma' / gamma.  (The
+// V-cycle of the last iteration runs before its stop test: one V-cycle more
+// per inner solve, one kernel less per iteration.)
+__global__ void __launch_bounds__(kFinBlock) k_fin_iter_mg(DevState* st, const double* pr, int nr,
+                                                           const double* pc, int nc, double omega_f) {
+  if (st->done || st->stop) return;
+  double rz, rr, cz, unused;
+  grid_sum2(pr, nr, rz, rr);
+  grid_sum2(pc, nc, cz, unused);
+  if (threadIdx.x == 0) {
+    st->rzf = rz;
+    st->rr = rr;
+    st->iters += 1;
+    if (!finite_d(rr) || !finite_d(rz)) { st->breakdown = 1; st->stop = 1; st->nonfinite = 1.0; }
+    if (rr <= st->tol2 || st->iters >= st->max_iters || !(rz > 0.0)) st->stop = 1;
+    const double gnew = omega_f * rz + cz;
+    if (!st->stop) {
+      if (!(gnew > 0.0) || !finite_d(gnew)) {
+        st->breakdown = 1;
+        st->stop = 1;
+        st->beta = 0.0;
+      } else {
+        st->beta = gnew / st->gamma;
+        st->gamma = gnew;
+      }
     }
   }
 }
