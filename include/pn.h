@@ -446,7 +446,8 @@ long long pn_batch_unknowns(const pn_batch* batch);
  * single-system multigrid even-parity path (bitwise the result of pn_solve
  * with the same z-chunk), each problem using its first system's scratch
  * vectors as the Krylov workspace and keeping its preconditioner and graph
- * (PN_ERR_ARG when some problem has a Neumann axis or zero extinction);
+ * (PN_ERR_ARG when some problem has a Neumann axis or zero extinction); up
+ * to four problems run at once, each on its own stream, from host threads;
  * SCHUR is refused.  info: NULL or a host array of
  * nprob * nrhs entries, one per system (seconds = wall time of the whole
  * batch, or of the system's own solve with SCHUR_MG).  Returns

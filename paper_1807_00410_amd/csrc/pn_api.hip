@@ -1638,6 +1638,20 @@ pn_status solve_padded_mg(pn_ctx* c, double tol, const pn_solve_opts& o, pn_solv
 
 bool mg_supported(const pn_ctx* c) { return c && mg_ok(c) && !c->use_lds; }
 
+pn_status prepare_mg_solve(pn_ctx* c, const pn_solve_opts& o) {
+  pn_status e = mg_alloc(c);
+  if (e != PN_OK) return e;
+  const int gi = o.graph_iters < 2 ? 2 : (o.graph_iters + 1) & ~1;  // as solve_impl
+  if (c->gexec_mg == nullptr || c->giters_mg != gi) {
+    if (c->gexec_mg) { hipGraphExecDestroy(c->gexec_mg); c->gexec_mg = nullptr; }
+    e = build_graph_mg(c, gi, &c->gexec_mg);
+    if (e != PN_OK) return e;
+    c->giters_mg = gi;
+  }
+  PN_HIP(hipStreamSynchronize(c->sstream));
+  return PN_OK;
+}
+
 pn_status borrow_workspace(pn_ctx* c, void* const* v) {
   float** dst[6] = {&c->r32[0], &c->r32[1], &c->s32, &c->p32, &c->q32, &c->d32};
   for (int i = 0; i < 6; ++i) *dst[i] = static_cast<float*>(v[i]);

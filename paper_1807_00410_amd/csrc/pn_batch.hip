@@ -19,11 +19,14 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <thread>
 #include <vector>
 
 #include "pn_internal.h"
 
 namespace {
+
+constexpr int kMgThreads = 4;  // host threads of the batched multigrid path (the GPU's hardware queues)
 
 struct Group {
   int order = 0, gen = 0;  // gen: some axis is not vacuum (general-boundary kernels)
@@ -470,22 +473,61 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
     // workspace; every system is solved by the single-system even-parity
     // multigrid path on its own Q and iterate (one captured graph per problem)
     B_HIP(hipStreamSynchronize(ss));
-    pn_status result = PN_OK;
-    int first_bad = -1;
+    // problems run concurrently on kMgThreads host threads (each problem has
+    // its own solve stream and workspace); largest first to the least-loaded
+    // thread.  Every system's arithmetic is independent of the schedule.
+    const int nth = std::max(1, std::min(kMgThreads, b->nprob));
+    std::vector<int> order(b->nprob);
+    for (int p = 0; p < b->nprob; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c2) { return b->prob[a]->n > b->prob[c2]->n; });
+    std::vector<std::vector<int>> work(nth);
+    std::vector<double> load(nth, 0.0);
+    for (int p : order) {
+      const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      work[t].push_back(p);
+      load[t] += (double)b->prob[p]->n;
+    }
+    std::vector<pn_status> sstat(b->nsys, PN_OK);
+    std::vector<pn_solve_info> sinfo(b->nsys);
+    std::vector<std::string> serr(b->nsys);
+    // everything that allocates or captures graphs first, on this thread: the
+    // worker threads then only launch work on their problems' own streams
     for (int p = 0; p < b->nprob; ++p) {
       pn_ctx* c = b->prob[p];
       pn_status e = borrow_workspace(c, b->sys_h[p * b->nrhs].vec);
-      if (e != PN_OK) { unborrow_workspace(c); return bfail(b, e, std::string("workspace: ") + pn_last_error(c)); }
-      for (int j = 0; j < b->nrhs; ++j) {
-        const int i = p * b->nrhs + j;
-        c->b32 = static_cast<float*>(b->sys_h[i].vec[BV_B]);
-        c->x64 = static_cast<double*>(b->sys_h[i].vec[BV_X64]);
-        pn_solve_info si;
-        const pn_status s = solve_padded_mg(c, tol, o, &si);
-        if (info) info[i] = si;
-        if (s != PN_OK && first_bad < 0) { first_bad = i; result = s; }
+      if (e == PN_OK) e = prepare_mg_solve(c, o);
+      if (e != PN_OK) {
+        const std::string m = pn_last_error(c);
+        for (int q = 0; q <= p; ++q) unborrow_workspace(b->prob[q]);
+        return bfail(b, e, "problem " + std::to_string(p) + ": " + m);
       }
-      unborrow_workspace(c);
+    }
+    int device = 0;
+    B_HIP(hipGetDevice(&device));
+    auto run = [&](int t) {
+      const bool dev_ok = hipSetDevice(device) == hipSuccess;
+      for (int p : work[t]) {
+        pn_ctx* c = b->prob[p];
+        for (int j = 0; j < b->nrhs; ++j) {
+          const int i = p * b->nrhs + j;
+          if (!dev_ok) { sstat[i] = PN_ERR_HIP; serr[i] = "hipSetDevice failed"; continue; }
+          c->b32 = static_cast<float*>(b->sys_h[i].vec[BV_B]);
+          c->x64 = static_cast<double*>(b->sys_h[i].vec[BV_X64]);
+          sstat[i] = solve_padded_mg(c, tol, o, &sinfo[i]);
+          if (sstat[i] != PN_OK) serr[i] = pn_last_error(c);
+        }
+      }
+    };
+    std::vector<std::thread> threads;
+    for (int t = 1; t < nth; ++t) threads.emplace_back(run, t);
+    run(0);
+    for (auto& th : threads) th.join();
+    for (int p = 0; p < b->nprob; ++p) unborrow_workspace(b->prob[p]);
+    pn_status result = PN_OK;
+    int first_bad = -1;
+    for (int i = 0; i < b->nsys; ++i) {
+      if (info) info[i] = sinfo[i];
+      if (sstat[i] != PN_OK && first_bad < 0) { first_bad = i; result = sstat[i]; }
     }
     for (int i = 0; i < b->nsys; ++i)
       B_HIP((launch_pack<double, double, 1>(b->prob[i / b->nrhs], (const double*)b->sys_h[i].vec[BV_X64], x[i], ss)));
@@ -493,7 +535,8 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
     B_HIP(hipStreamWaitEvent(b->stream, b->ev_out, 0));
     B_HIP(hipStreamSynchronize(ss));
     if (first_bad >= 0)
-      bfail(b, result, "system " + std::to_string(first_bad) + ": " + pn_status_string(result));
+      bfail(b, result, "system " + std::to_string(first_bad) + ": " + pn_status_string(result) + " (" +
+                           serr[first_bad] + ")");
     return result;
   }
   const int gi = o.graph_iters < 2 ? 2 : (o.graph_iters + 1) & ~1;  // even: r ends in r0

@@ -200,6 +200,10 @@ void free_ctx(pn_ctx* c);
 pn_status solve_padded_mg(pn_ctx* c, double tol, const pn_solve_opts& o, pn_solve_info* info);
 // True when the multigrid even-parity solve applies to the context.
 bool mg_supported(const pn_ctx* c);
+// Everything of the multigrid solve that allocates or captures (levels,
+// coupling terms, the captured iteration graph for o.graph_iters), so that
+// later solves of the context only launch work (needs the workspace).
+pn_status prepare_mg_solve(pn_ctx* c, const pn_solve_opts& o);
 // Points the FP32 scratch vectors (r0, r1, s, p, q, d) of a context created
 // without workspace at caller-owned padded buffers v[0..5] and allocates the
 // small owned parts (bfloat16 preconditioner, device scalars, partials) on
