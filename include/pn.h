@@ -160,9 +160,10 @@ typedef struct {
  * every transport neighbour present, formed from the medium inside the
  * kernels: no extra memory traffic); the inner stop then tests the W-weighted
  * residual.  Needs the register-window stencil (PN_ERR_ARG with pn_set_tiles
- * or PN_FP64).  AUTO: SCHUR_MG on the register-window stencil (CG_EQ when an
- * axis is Neumann or some cell has zero extinction), CG on the LDS-tiled one;
- * the batched solve treats AUTO as CG_EQ.  The FP64 refinement checks the true, unweighted residual
+ * or PN_FP64).  AUTO: on the register-window stencil SCHUR_MG for odd orders
+ * with at least 2^18 even-band unknowns, SCHUR otherwise (CG_EQ when an axis
+ * is Neumann or some cell has zero extinction); CG on the LDS-tiled one; the
+ * batched solve treats AUTO as CG_EQ.  The FP64 refinement checks the true, unweighted residual
  * ||Q - A x|| in every case. */
 #define PN_VARIANT_AUTO 0
 #define PN_VARIANT_CGLS 1

@@ -1016,6 +1016,21 @@ constexpr int kMgCoarsest = 5;        // coarsen until every axis has at most th
 
 static bool mg_ok(const pn_ctx* c) { return schur_ok(c) && c->even.nk >= 1 && c->even.nk <= kMgMaxEven; }
 
+// AUTO's choice of the multigrid form: odd orders (with even N the top band
+// stays in the even set and the per-coefficient blocks miss its coupling to
+// l = N - 2: 1.65x fewer iterations against Jacobi, not enough for the V-cycle's
+// cost) with at least 2^18 even-band unknowns (below that its ten small
+// launches per iteration cost more than the iterations they save).
+constexpr long long kMgAutoMinEven = 1LL << 18;
+static bool mg_auto(const pn_ctx* c) {
+  long long ne = 0;
+  for (int s = 0; s < c->even.nk; ++s) {
+    const int k = c->even.k[s];
+    ne += (long long)c->ext[k][0] * c->ext[k][1] * c->ext[k][2];
+  }
+  return (c->order & 1) && ne >= kMgAutoMinEven;
+}
+
 static long long mg_points(const MgGeom& g, int s) { return (long long)g.ext[s][0] * g.ext[s][1] * g.ext[s][2]; }
 
 static int mg_blocks(const MgGeom& g) {
@@ -1420,9 +1435,9 @@ static pn_status solve_impl(pn_ctx* c, double tol, const pn_solve_opts& o, pn_so
   // ping-pong, the A^T pass streams two).
   // FP32 even-parity PCG (Schur complement): SCHUR, and AUTO on the
   // register-window stencil when no axis is Neumann
-  // with the multigrid preconditioner: SCHUR_MG, and AUTO whenever the even-parity form applies
+  // with the multigrid preconditioner: SCHUR_MG, and AUTO for large odd-order problems
   const bool mg = (sizeof(T) == 4) && mg_ok(c) && !c->use_lds &&
-                  (o.variant == PN_VARIANT_SCHUR_MG || o.variant == PN_VARIANT_AUTO);
+                  (o.variant == PN_VARIANT_SCHUR_MG || (o.variant == PN_VARIANT_AUTO && mg_auto(c)));
   const bool schur = (sizeof(T) == 4) && schur_ok(c) &&
                      (mg || o.variant == PN_VARIANT_SCHUR || (o.variant == PN_VARIANT_AUTO && !c->use_lds));
   const bool cg = (sizeof(T) == 4) && !schur && o.variant != PN_VARIANT_CGLS;
