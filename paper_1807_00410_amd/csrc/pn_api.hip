@@ -180,6 +180,7 @@ static void free_all(pn_ctx* c) {
   if (c->gexec_mg) hipGraphExecDestroy(c->gexec_mg);
   hipFree(c->mg_terms);
   hipFree(c->mg_partials);
+  hipFree(c->mg_tail);
   for (int L = 0; L < kMgMaxLevels; ++L) {
     hipFree(c->mg_op[L]); hipFree(c->mg_r[L]); hipFree(c->mg_z[L]); hipFree(c->mg_zt[L]); hipFree(c->mg_idg[L]);
   }
@@ -1040,6 +1041,48 @@ static int mg_blocks(const MgGeom& g) {
   return (int)std::max<long long>(1, std::min<long long>(b, 2048));
 }
 
+// Grid of the aggregating down pass from level f to level c: blocks of
+// kBlock / kMgAggLanes aggregates of the largest coarse (x, y) plane, chunks of
+// mg_down_chunk coarse z planes of the deepest slot, slots.
+static int mg_down_chunk(const MgGeom& f) { return f.off[f.nk] > (1 << 20) ? 2 : 1; }
+
+static dim3 mg_down_grid(const MgGeom& f, const MgGeom& c) {
+  long long na = 0;
+  int zc = 0;
+  for (int s = 0; s < c.nk; ++s) {
+    na = std::max(na, (long long)c.ext[s][0] * c.ext[s][1]);
+    zc = std::max(zc, c.ext[s][2]);
+  }
+  const long long b = (na * kMgAggLanes + kBlock - 1) / kBlock;
+  const int ch = mg_down_chunk(f);
+  return dim3((unsigned)b, (zc + ch - 1) / ch, c.nk);
+}
+
+// z planes per thread of the up pass on level f: a march of 4 planes where
+// the level has more than 2^20 points (fewer, larger blocks keep z' of the
+// plane below in registers), one plane below (more threads in flight).
+static int mg_up_chunk(const MgGeom& f) { return f.off[f.nk] > (1 << 20) ? 4 : 1; }
+
+// Grid of the up pass on level f: blocks of the largest (x, y) plane, z
+// chunks of the deepest slot, slots.
+static dim3 mg_up_grid(const MgGeom& f) {
+  long long np = 0;
+  int ez = 0;
+  for (int s = 0; s < f.nk; ++s) {
+    np = std::max(np, (long long)f.ext[s][0] * f.ext[s][1]);
+    ez = std::max(ez, f.ext[s][2]);
+  }
+  const int ch = mg_up_chunk(f);
+  return dim3((unsigned)((np + kBlock - 1) / kBlock), (ez + ch - 1) / ch, f.nk);
+}
+
+static int mg_restrict_blocks(const MgGeom& g) {
+  long long m = 0;
+  for (int s = 0; s < g.nk; ++s) m = std::max(m, mg_points(g, s));
+  const long long per = (long long)kBlock * kMgRestrictPer;
+  return (int)std::max<long long>(1, std::min<long long>((m + per - 1) / per, 2048));
+}
+
 // Level geometry, coupling terms and buffers (once per context).
 static pn_status mg_alloc(pn_ctx* c) {
   if (c->mg_levels > 0) return PN_OK;
@@ -1100,7 +1143,41 @@ static pn_status mg_alloc(pn_ctx* c) {
     PN_HIP(hipMalloc(&c->mg_zt[L], sizeof(float) * n));
     PN_HIP(hipMalloc(&c->mg_idg[L], sizeof(float) * n));
   }
-  c->mg_npart = levels == 1 ? 1 : mg_blocks(g[1]) * f.nk;
+  // the tail: the first level L0 < levels at which every slot has at most one
+  // point per thread of the tail's block (larger levels keep the wide
+  // kernels: one block per slot has too little parallelism there) and its
+  // levels L0..levels, plus the scratch, fit the kernel's LDS
+  c->mg_tail_L0 = 0;
+  for (int L0 = 1; L0 < levels && c->mg_tail_L0 == 0; ++L0) {
+    bool fits = true;
+    for (int s = 0; s < f.nk && fits; ++s) {
+      long long need = mg_points(g[L0 + 1], s);
+      for (int L = L0; L <= levels; ++L) need += 2 * mg_points(g[L], s);
+      fits = need <= kMgTailLds && mg_points(g[L0], s) <= kFinBlock;
+    }
+    if (fits) c->mg_tail_L0 = L0;
+  }
+  if (c->mg_tail_L0 > 0) {
+    MgTail tl;
+    std::memset(&tl, 0, sizeof(tl));
+    tl.L0 = c->mg_tail_L0;
+    tl.Lc = levels;
+    for (int L = 0; L <= levels; ++L) {
+      tl.g[L] = g[L];
+      tl.op[L] = c->mg_op[L];
+      tl.idg[L] = c->mg_idg[L];
+    }
+    PN_HIP(hipMalloc(&c->mg_tail, sizeof(MgTail)));
+    PN_HIP(hipMemcpy(c->mg_tail, &tl, sizeof(MgTail), hipMemcpyHostToDevice));
+  }
+  if (levels == 1) {
+    c->mg_npart = 1;
+  } else if (c->mg_tail_L0 == 1) {
+    c->mg_npart = f.nk;
+  } else {
+    const dim3 gu = mg_up_grid(g[1]);
+    c->mg_npart = (int)(gu.x * gu.y * gu.z);
+  }
   PN_HIP(hipMalloc(&c->mg_partials, sizeof(double) * 2 * c->mg_npart));
   c->mg_levels = levels;
   return PN_OK;
@@ -1120,18 +1197,6 @@ static pn_status mg_setup_ops(pn_ctx* c, const float* m32, const float* invdo, h
     PN_HIP(hipGetLastError());
   }
   return PN_OK;
-}
-
-// Grid of the tiled aggregation kernels over level f (coarse level c): tiles
-// of the largest (x, y) extent, coarse z planes of the deepest slot, slots.
-static dim3 mg_tiles(const MgGeom& f, const MgGeom& c) {
-  int tx = 0, ty = 0, zc = 0;
-  for (int s = 0; s < f.nk; ++s) {
-    tx = std::max(tx, (f.ext[s][0] + kMgTile - 1) / kMgTile);
-    ty = std::max(ty, (f.ext[s][1] + kMgTile - 1) / kMgTile);
-    zc = std::max(zc, c.ext[s][2]);
-  }
-  return dim3(tx * ty, zc, f.nk);
 }
 
 // Preconditioner setup of the even-parity solve: 1 / d_o in the odd slots of
@@ -1164,20 +1229,29 @@ static const float* mg_final(const pn_ctx* c, int L) { return L == c->mg_levels 
 static hipError_t mg_vcycle(pn_ctx* c, const float* r, hipStream_t st) {
   const MgGeom* g = c->mg_geom;
   const int Lc = c->mg_levels;
+  const int Lt = c->mg_tail_L0 > 0 ? c->mg_tail_L0 : Lc;  // levels below Lt run one kernel per pass
   const DevState* ds = c->st;
-  hipLaunchKernelGGL(k_mg_restrict0, dim3(mg_blocks(g[1]), g[1].nk), dim3(kBlock), 0, st, c->mg_fine, g[1], r,
+  hipLaunchKernelGGL(k_mg_restrict0, dim3(mg_restrict_blocks(g[1]), g[1].nk), dim3(kBlock), 0, st, c->mg_fine, g[1], r,
                      (const float*)c->mg_idg[1], c->mg_r[1], c->mg_z[1], kMgOmega, ds);
-  for (int L = 1; L < Lc; ++L)
-    hipLaunchKernelGGL(k_mg_down, mg_tiles(g[L], g[L + 1]), dim3(kBlock), 0, st, g[L], g[L + 1],
+  for (int L = 1; L < Lt; ++L)
+    hipLaunchKernelGGL(k_mg_down, mg_down_grid(g[L], g[L + 1]), dim3(kBlock), 0, st, g[L], g[L + 1],
                        (const float4*)c->mg_op[L], (const float*)c->mg_r[L], (const float*)c->mg_z[L],
-                       (const float*)c->mg_idg[L + 1], c->mg_r[L + 1], c->mg_z[L + 1], kMgOmega, ds);
-  hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(kFinBlock), 0, st, g[Lc], (const float4*)c->mg_op[Lc],
-                     (const float*)c->mg_r[Lc], c->mg_z[Lc], kMgSweeps, kMgOmega,
-                     Lc == 1 ? c->mg_partials : (double*)nullptr, ds);
-  for (int L = Lc - 1; L >= 1; --L)
-    hipLaunchKernelGGL(k_mg_up, dim3(mg_blocks(g[L]), g[L].nk), dim3(kBlock), 0, st, g[L], g[L + 1],
+                       (const float*)c->mg_idg[L + 1], c->mg_r[L + 1], c->mg_z[L + 1], kMgOmega,
+                       mg_down_chunk(g[L]), ds);
+  if (c->mg_tail_L0 > 0) {
+    hipLaunchKernelGGL(k_mg_tail, dim3(g[Lt].nk), dim3(kFinBlock), 0, st, (const MgTail*)c->mg_tail,
+                       (const float*)c->mg_r[Lt], (const float*)c->mg_z[Lt], c->mg_zt[Lt], kMgSweeps, kMgOmega,
+                       Lt == 1 ? c->mg_partials : (double*)nullptr, ds);
+  } else {
+    hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(kFinBlock), 0, st, g[Lc], (const float4*)c->mg_op[Lc],
+                       (const float*)c->mg_r[Lc], c->mg_z[Lc], kMgSweeps, kMgOmega,
+                       Lc == 1 ? c->mg_partials : (double*)nullptr, ds);
+  }
+  for (int L = Lt - 1; L >= 1; --L)
+    hipLaunchKernelGGL(k_mg_up, mg_up_grid(g[L]), dim3(kBlock), 0, st, g[L], g[L + 1],
                        (const float4*)c->mg_op[L], (const float*)c->mg_r[L], (const float*)c->mg_z[L],
-                       mg_final(c, L + 1), c->mg_zt[L], kMgOmega, L == 1 ? c->mg_partials : (double*)nullptr, ds);
+                       mg_final(c, L + 1), c->mg_zt[L], kMgOmega, mg_up_chunk(g[L]),
+                       L == 1 ? c->mg_partials : (double*)nullptr, ds);
   return hipGetLastError();
 }
 

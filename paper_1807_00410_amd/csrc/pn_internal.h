@@ -106,6 +106,8 @@ struct pn_ctx {
   float* mg_idg[kMgMaxLevels] = {};  // 1 / diag per level (the same reciprocal every Jacobi step uses)
   double* mg_partials = nullptr;
   int mg_npart = 0;  // block partial pairs of <P^T r, V(P^T r)>
+  int mg_tail_L0 = 0;  // first level of the one-launch tail of the V-cycle (0: none)
+  MgTail* mg_tail = nullptr;
   int prec_ready = 0;  // bit 0: m16 formed, bit 1: the multigrid operators formed
   hipGraphExec_t gexec_mg = nullptr;
   int giters_mg = 0;

@@ -58,4 +58,14 @@ struct MgTerms {
   float c2[kMgMaxEven][3][kMgMaxTerms];
 };
 
+// Levels L0..Lc (the coarsest) of the V-cycle run in one kernel, one block
+// per slot in LDS: the geometry and the operators of every level, in device
+// memory.
+struct MgTail {
+  int L0, Lc;
+  MgGeom g[kMgMaxLevels];
+  const float4* op[kMgMaxLevels];
+  const float* idg[kMgMaxLevels];
+};
+
 }  // namespace pn

@@ -27,6 +27,15 @@ __device__ __forceinline__ int mg_points(const MgGeom& g, int s) { return g.ext[
 // scaling in every sweep, so the V-cycle stays symmetric).
 __device__ __forceinline__ float mg_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
 
+// The block of a 3D grid in the order x, y, z, from a linear order that gives
+// each XCD a contiguous range (neighbouring z planes of a slot then share an
+// L2: their halo planes are read once per XCD).
+__device__ __forceinline__ int3 mg_block() {
+  const int nx = gridDim.x, ny = gridDim.y;
+  const int q = xcd_remap(blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z), nx * ny * gridDim.z);
+  return make_int3(q % nx, (q / nx) % ny, q / (nx * ny));
+}
+
 // Fine face weight of slot s between the padded point pidx and pidx + e_d.
 __device__ __forceinline__ double mg_fine_w(const MgFine& f, const MgTerms* __restrict__ t,
                                             const float* __restrict__ invdo, int s, long long pidx, int d) {
@@ -120,9 +129,12 @@ static __global__ void __launch_bounds__(kBlock) k_mg_coarsen(const MgGeom gf, c
 
 // r1 = P^T r: the fine residual (even slots of the padded r) summed over each
 // aggregate, and z1 = omega r1 / diag (the first damped Jacobi sweep of the
-// level-1 V-cycle, from zero).  One thread per aggregate: a wave reads 128
-// consecutive fine x of each of its four (y, z) rows (tiles of 16 x 16 fine
-// columns read this layout in 64-byte pieces and were measured 2x slower).
+// level-1 V-cycle, from zero).  A thread sums kMgRestrictPer aggregates
+// kBlock apart, all 8 kMgRestrictPer loads issued before the first sum; a wave
+// reads 128 consecutive fine x of each of its four (y, z) rows.  Grid:
+// (blocks, slots).
+constexpr int kMgRestrictPer = 2;
+
 static __global__ void __launch_bounds__(kBlock) k_mg_restrict0(const MgFine f, const MgGeom g1,
                                                                 const float* __restrict__ r,
                                                                 const float* __restrict__ idg1,
@@ -134,114 +146,171 @@ static __global__ void __launch_bounds__(kBlock) k_mg_restrict0(const MgFine f, 
   const int fe[3] = {f.ext[s][0], f.ext[s][1], f.ext[s][2]};
   const float* rs = r + (long long)f.k[s] * f.cs;
   const int PX = f.PX, PY = f.PY;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    int X, Y, Z;
-    mg_xyz(g1, s, i, X, Y, Z);
-    float acc = 0.f;
-    for (int c = 0; c < 8; ++c) {
-      const int x = 2 * X + (c & 1), y = 2 * Y + ((c >> 1) & 1), z = 2 * Z + (c >> 2);
-      if (x >= fe[0] || y >= fe[1] || z >= fe[2]) continue;
-      acc += rs[((z + 1) * PY + (y + 1)) * PX + (x + 1)];
+  for (int i0 = blockIdx.x * (kBlock * kMgRestrictPer) + threadIdx.x; i0 < n;
+       i0 += gridDim.x * (kBlock * kMgRestrictPer)) {
+    float v[kMgRestrictPer][8];
+#pragma unroll
+    for (int u = 0; u < kMgRestrictPer; ++u) {
+      const int i = i0 + u * kBlock;
+      int X = 0, Y = 0, Z = 0;
+      if (i < n) mg_xyz(g1, s, i, X, Y, Z);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int x = 2 * X + (c & 1), y = 2 * Y + ((c >> 1) & 1), z = 2 * Z + (c >> 2);
+        v[u][c] = (i < n && x < fe[0] && y < fe[1] && z < fe[2]) ? rs[((z + 1) * PY + (y + 1)) * PX + (x + 1)] : 0.f;
+      }
     }
-    const long long j = g1.off[s] + i;
-    r1[j] = acc;
-    z1[j] = omega * acc * idg1[j];
+#pragma unroll
+    for (int u = 0; u < kMgRestrictPer; ++u) {
+      const int i = i0 + u * kBlock;
+      if (i >= n) continue;
+      int X, Y, Z;
+      mg_xyz(g1, s, i, X, Y, Z);
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int x = 2 * X + (c & 1), y = 2 * Y + ((c >> 1) & 1), z = 2 * Z + (c >> 2);
+        if (x < fe[0] && y < fe[1] && z < fe[2]) acc += v[u][c];
+      }
+      const long long j = g1.off[s] + i;
+      r1[j] = acc;
+      z1[j] = omega * acc * idg1[j];
+    }
   }
 }
 
-// (A z)(x) - diag(x) z(x) for the explicit operator, z given pointwise by ZF.
-template <typename ZF>
-__device__ __forceinline__ float mg_offdiag(const MgGeom& g, int s, const float4* __restrict__ op, const float4& o,
-                                            int x, int y, int z, ZF zf) {
-  const int e[3] = {g.ext[s][0], g.ext[s][1], g.ext[s][2]};
-  float acc = 0.f;
-  if (x + 1 < e[0]) acc -= o.y * zf(x + 1, y, z);
-  if (y + 1 < e[1]) acc -= o.z * zf(x, y + 1, z);
-  if (z + 1 < e[2]) acc -= o.w * zf(x, y, z + 1);
-  if (x >= 1) acc -= op[mg_at(g, s, x - 1, y, z)].y * zf(x - 1, y, z);
-  if (y >= 1) acc -= op[mg_at(g, s, x, y - 1, z)].z * zf(x, y - 1, z);
-  if (z >= 1) acc -= op[mg_at(g, s, x, y, z - 1)].w * zf(x, y, z - 1);
-  return acc;
-}
-
-// Tiles of the aggregating down pass: 16 x 16 points (x, y) per block of 256
-// threads, each thread two z planes (one coarse plane); a wave holds four
-// rows of 16, so the x partner of a lane is lane ^ 1 and the y partner
-// lane ^ 16, and the 2 x 2 x 2 sums close with two shuffles.  Grid: (tiles of
-// the (x, y) extent, coarse z planes, slots).
-constexpr int kMgTile = 16;
+// The aggregating down pass maps the lanes of a wave onto 16 aggregates of a
+// coarse (X, Y) row-major plane, four lanes each (lane = 4 a + child, child =
+// (y & 1) * 2 + (x & 1)); a lane marches its fine column through `zchunk`
+// coarse planes (2 zchunk fine planes), keeping z and the -z face weight of
+// the plane below in registers, and each coarse plane's 2 x 2 x 2 sum closes
+// with the shuffles ^1 (x partner) and ^2 (y partner), for any extents.
+// Grid: (blocks of 64 aggregates of the largest coarse plane, chunks of
+// coarse z planes of the deepest slot, slots), taken XCD-contiguous.
+constexpr int kMgAggLanes = 4;
 
 __device__ __forceinline__ float mg_quad_sum(float v) {
   v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, kMgTile);
+  v += __shfl_xor(v, 2);
   return v;
 }
 
 // Down the V-cycle at level L (z_L = omega r_L / diag already formed):
 // r_{L+1} = P^T (r_L - A_L z_L) and the first sweep of level L + 1, z_{L+1} =
-// omega r_{L+1} / diag.  Tiled over the points of level L (above).
+// omega r_{L+1} / diag.
 static __global__ void __launch_bounds__(kBlock) k_mg_down(const MgGeom gf, const MgGeom gc,
                                                            const float4* __restrict__ op, const float* __restrict__ r,
                                                            const float* __restrict__ zl,
                                                            const float* __restrict__ idgc, float* __restrict__ rc,
-                                                           float* __restrict__ zc, float omega,
+                                                           float* __restrict__ zc, float omega, int zchunk,
                                                            const DevState* __restrict__ st) {
   if (st->stop) return;
-  const int s = blockIdx.z, Z = blockIdx.y;
+  const int3 bk = mg_block();
+  const int s = bk.z, Z0 = bk.y * zchunk;
   const int fx = gf.ext[s][0], fy = gf.ext[s][1], fz = gf.ext[s][2];
-  const int ntx = (fx + kMgTile - 1) / kMgTile;
-  const int x = (blockIdx.x % ntx) * kMgTile + (threadIdx.x & (kMgTile - 1));
-  const int y = (blockIdx.x / ntx) * kMgTile + (threadIdx.x / kMgTile);
-  auto zf = [&](int xx, int yy, int zz) { return zl[mg_at(gf, s, xx, yy, zz)]; };
-  float acc = 0.f;
-  if (x < fx && y < fy) {
-    for (int z = 2 * Z; z < 2 * Z + 2 && z < fz; ++z) {
-      const long long j = mg_at(gf, s, x, y, z);
-      const float4 o = op[j];
-      acc += r[j] - (o.x * zl[j] + mg_offdiag(gf, s, op, o, x, y, z, zf));
+  const int cx = gc.ext[s][0], na = cx * gc.ext[s][1], cz = gc.ext[s][2];
+  const int t = bk.x * kBlock + threadIdx.x;
+  const int a = t / kMgAggLanes, ch = t % kMgAggLanes;
+  const int Y = a / cx, X = a - Y * cx;
+  const int x = 2 * X + (ch & 1), y = 2 * Y + (ch >> 1);
+  const bool in = a < na && x < fx && y < fy;
+  const int plane = fx * fy;
+  float zm = 0.f, wm = 0.f, zp = 0.f;  // z of the planes z - 1 and z, the +z weight of plane z - 1
+  if (in && 2 * Z0 < fz) {
+    const long long j0 = mg_at(gf, s, x, y, 2 * Z0);
+    if (Z0 >= 1) {
+      zm = zl[j0 - plane];
+      wm = op[j0 - plane].w;
     }
+    zp = zl[j0];
   }
-  acc = mg_quad_sum(acc);
-  const int X = x >> 1, Y = y >> 1;
-  if (!(x & 1) && !(y & 1) && X < gc.ext[s][0] && Y < gc.ext[s][1] && Z < gc.ext[s][2]) {
-    const long long jc = mg_at(gc, s, X, Y, Z);
-    rc[jc] = acc;
-    zc[jc] = omega * acc * idgc[jc];
+  for (int Z = Z0; Z < Z0 + zchunk; ++Z) {  // uniform over the wave (the shuffles)
+    float acc = 0.f;
+    if (in) {
+      for (int z = 2 * Z; z < 2 * Z + 2 && z < fz; ++z) {
+        const long long j = mg_at(gf, s, x, y, z);
+        const float4 o = op[j];
+        const float zn = z + 1 < fz ? zl[j + plane] : 0.f;
+        float od = 0.f;
+        if (x + 1 < fx) od -= o.y * zl[j + 1];
+        if (y + 1 < fy) od -= o.z * zl[j + fx];
+        if (z + 1 < fz) od -= o.w * zn;
+        if (x >= 1) od -= op[j - 1].y * zl[j - 1];
+        if (y >= 1) od -= op[j - fx].z * zl[j - fx];
+        if (z >= 1) od -= wm * zm;
+        acc += r[j] - (o.x * zp + od);
+        zm = zp;
+        zp = zn;
+        wm = o.w;
+      }
+    }
+    acc = mg_quad_sum(acc);
+    if (ch == 0 && a < na && Z < cz) {
+      const long long jc = mg_at(gc, s, X, Y, Z);
+      rc[jc] = acc;
+      zc[jc] = omega * acc * idgc[jc];
+    }
   }
 }
 
 // Up the V-cycle at level L: z' = z_L + P z_{L+1}, then one damped Jacobi
-// sweep z'' = z' + omega (r_L - A_L z') / diag into zo.  With `partials`,
-// also the block sums of <r_L, z''> (level 1: the coarse part of <r, B r>).
+// sweep z'' = z' + omega (r_L - A_L z') / diag into zo.  A thread marches one
+// (x, y) column through `zchunk` z planes, keeping z' and the -z face weight
+// of the plane below in registers.  With `partials`, also the block sums of
+// <r_L, z''> (level 1: the coarse part of <r, B r>).  Grid: (blocks of the
+// largest (x, y) plane, z chunks of the deepest slot, slots), taken
+// XCD-contiguous.
+
 static __global__ void __launch_bounds__(kBlock) k_mg_up(const MgGeom gf, const MgGeom gc,
                                                          const float4* __restrict__ op, const float* __restrict__ r,
                                                          const float* __restrict__ zl, const float* __restrict__ zc,
-                                                         float* __restrict__ zo, float omega,
+                                                         float* __restrict__ zo, float omega, int zchunk,
                                                          double* __restrict__ partials,
                                                          const DevState* __restrict__ st) {
   if (st->stop) return;
-  const int s = blockIdx.y;
-  const int n = mg_points(gf, s);
-  auto zf = [&](int x, int y, int z) {
-    return zl[mg_at(gf, s, x, y, z)] + zc[mg_at(gc, s, x >> 1, y >> 1, z >> 1)];
+  const int3 bk = mg_block();
+  const int s = bk.z;
+  const int ex = gf.ext[s][0], ey = gf.ext[s][1], ez = gf.ext[s][2];
+  const int col = bk.x * kBlock + threadIdx.x;
+  const int y = col / ex, x = col - y * ex;
+  const int z0 = bk.y * zchunk;
+  auto zf = [&](int xx, int yy, int zz) {
+    return zl[mg_at(gf, s, xx, yy, zz)] + zc[mg_at(gc, s, xx >> 1, yy >> 1, zz >> 1)];
   };
   double s0 = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    int x, y, z;
-    mg_xyz(gf, s, i, x, y, z);
-    const long long j = gf.off[s] + i;
-    const float4 o = op[j];
-    const float zp = zf(x, y, z);
-    const float rv = r[j];
-    const float out = zp + omega * (rv - (o.x * zp + mg_offdiag(gf, s, op, o, x, y, z, zf))) * mg_rcp(o.x);
-    zo[j] = out;
-    s0 += (double)(rv * out);
+  if (y < ey && z0 < ez) {
+    const int z1 = min(z0 + zchunk, ez);
+    float zm = 0.f, wm = 0.f;  // z' and the +z weight of plane z - 1
+    if (z0 >= 1) {
+      zm = zf(x, y, z0 - 1);
+      wm = op[mg_at(gf, s, x, y, z0 - 1)].w;
+    }
+    float zp = zf(x, y, z0);
+    for (int z = z0; z < z1; ++z) {
+      const long long j = mg_at(gf, s, x, y, z);
+      const float4 o = op[j];
+      const float zn = z + 1 < ez ? zf(x, y, z + 1) : 0.f;
+      float acc = 0.f;
+      if (x + 1 < ex) acc -= o.y * zf(x + 1, y, z);
+      if (y + 1 < ey) acc -= o.z * zf(x, y + 1, z);
+      if (z + 1 < ez) acc -= o.w * zn;
+      if (x >= 1) acc -= op[j - 1].y * zf(x - 1, y, z);
+      if (y >= 1) acc -= op[j - ex].z * zf(x, y - 1, z);
+      if (z >= 1) acc -= wm * zm;
+      const float rv = r[j];
+      const float out = zp + omega * (rv - (o.x * zp + acc)) * mg_rcp(o.x);
+      zo[j] = out;
+      s0 += (double)(rv * out);
+      zm = zp;
+      zp = zn;
+      wm = o.w;
+    }
   }
   if (partials) {
     double unused = 0.0;
     block_sum2(s0, unused);
     if (threadIdx.x == 0) {
-      const int b = blockIdx.y * gridDim.x + blockIdx.x;
+      const int b = (bk.z * gridDim.y + bk.y) * gridDim.x + bk.x;
       partials[2 * b] = s0;
       partials[2 * b + 1] = 0.0;
     }
@@ -326,6 +395,240 @@ static __global__ void __launch_bounds__(kFinBlock) k_mg_coarsest(const MgGeom g
       for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) a += red[wv];
       partials[0] = a;
       partials[1] = 0.0;
+    }
+  }
+}
+
+// The small levels L0..Lc of the V-cycle in one launch: block s holds slot s
+// of every level from L0 in LDS (r_L and z_L of each level, then a scratch
+// array of the size of level L0 + 1), takes r_L0 and z_L0 = omega r_L0 / diag
+// from the kernels before, and runs the same steps as k_mg_down,
+// k_mg_coarsest and k_mg_up in the same arithmetic order (a thread issues the
+// operator loads of a group of its points before using any, the level data
+// being in LDS, so a pass waits on global memory about once): the down passes to
+// Lc, `sweeps` - 1 further sweeps there, the up passes back to L0, whose
+// result goes to zout.  With `partials` (L0 = 1), partials[2 s] = <r_1, z''>
+// over the slot.  Grid: (slots); kMgTailLds bounds what one slot may need.
+constexpr int kMgTailLds = 15360;
+constexpr int kMgTailPer = 4;  // points per thread whose operator loads are issued together
+
+__device__ __forceinline__ int mg_tail_points(const MgTail* t, int L, int s) {
+  return t->g[L].ext[s][0] * t->g[L].ext[s][1] * t->g[L].ext[s][2];
+}
+
+static __global__ void __launch_bounds__(kFinBlock) k_mg_tail(const MgTail* __restrict__ t,
+                                                              const float* __restrict__ r0,
+                                                              const float* __restrict__ z0,
+                                                              float* __restrict__ zout, int sweeps, float omega,
+                                                              double* __restrict__ partials,
+                                                              const DevState* __restrict__ st) {
+  __shared__ float lds[kMgTailLds];
+  __shared__ double red[kFinBlock / 64];
+  if (st->stop) return;
+  const int s = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+  const int L0 = t->L0, Lc = t->Lc;
+  auto base = [&](int L) {  // r_L at base(L), z_L after it; the scratch at base(Lc + 1)
+    int o = 0;
+    for (int l = L0; l < L; ++l) o += 2 * mg_tail_points(t, l, s);
+    return o;
+  };
+  {
+    const int n = mg_tail_points(t, L0, s);
+    const long long off = t->g[L0].off[s];
+    float* rl = lds + base(L0);
+    for (int i0 = tid; i0 < n; i0 += kMgTailPer * nth) {
+      float rv[kMgTailPer], zv[kMgTailPer];
+#pragma unroll
+      for (int u = 0; u < kMgTailPer; ++u) {
+        const int i = i0 + u * nth;
+        rv[u] = i < n ? r0[off + i] : 0.f;
+        zv[u] = i < n ? z0[off + i] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kMgTailPer; ++u) {
+        const int i = i0 + u * nth;
+        if (i < n) { rl[i] = rv[u]; rl[n + i] = zv[u]; }
+      }
+    }
+  }
+  __syncthreads();
+  // down: r_{L+1} = P^T (r_L - A_L z_L), z_{L+1} = omega r_{L+1} / diag
+  for (int L = L0; L < Lc; ++L) {
+    const MgGeom& gf = t->g[L];
+    const MgGeom& gc = t->g[L + 1];
+    const int fx = gf.ext[s][0], fy = gf.ext[s][1], fz = gf.ext[s][2];
+    const int cx = gc.ext[s][0], cy = gc.ext[s][1];
+    const int nf = fx * fy * fz, nc = cx * cy * gc.ext[s][2];
+    const float* rl = lds + base(L);
+    const float* zl = rl + nf;
+    float* rc = lds + base(L + 1);
+    float* zc = rc + nc;
+    const float4* op = t->op[L] + gf.off[s];
+    const float* idgc = t->idg[L + 1] + gc.off[s];
+    for (int I = tid; I < nc; I += nth) {
+      const int X = I % cx, Y = (I / cx) % cy, Z = I / (cx * cy);
+      // the operator entries of the 8 children (own and the -x, -y, -z face
+      // weights), all loads in flight before the first use
+      float4 o[8];
+      float wm[8][3];
+#pragma unroll
+      for (int c8 = 0; c8 < 8; ++c8) {
+        const int x = 2 * X + (c8 & 1), y = 2 * Y + ((c8 >> 1) & 1), z = 2 * Z + (c8 >> 2);
+        const bool in = x < fx && y < fy && z < fz;
+        const int j = (z * fy + y) * fx + x;
+        o[c8] = in ? op[j] : make_float4(1.f, 0.f, 0.f, 0.f);
+        wm[c8][0] = in && x >= 1 ? op[j - 1].y : 0.f;
+        wm[c8][1] = in && y >= 1 ? op[j - fx].z : 0.f;
+        wm[c8][2] = in && z >= 1 ? op[j - fx * fy].w : 0.f;
+      }
+      float a[4];
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        const int x = 2 * X + (ch & 1), y = 2 * Y + (ch >> 1);
+        float acc = 0.f;
+        if (x < fx && y < fy) {
+#pragma unroll
+          for (int dz = 0; dz < 2; ++dz) {
+            const int z = 2 * Z + dz;
+            if (z < fz) {
+              const int c8 = ch + 4 * dz;
+              const int j = (z * fy + y) * fx + x;
+              const float4 oo = o[c8];
+              float od = 0.f;
+              if (x + 1 < fx) od -= oo.y * zl[j + 1];
+              if (y + 1 < fy) od -= oo.z * zl[j + fx];
+              if (z + 1 < fz) od -= oo.w * zl[j + fx * fy];
+              if (x >= 1) od -= wm[c8][0] * zl[j - 1];
+              if (y >= 1) od -= wm[c8][1] * zl[j - fx];
+              if (z >= 1) od -= wm[c8][2] * zl[j - fx * fy];
+              acc += rl[j] - (oo.x * zl[j] + od);
+            }
+          }
+        }
+        a[ch] = acc;
+      }
+      const float v = (a[0] + a[1]) + (a[2] + a[3]);
+      rc[I] = v;
+      zc[I] = omega * v * idgc[I];
+    }
+    __syncthreads();
+  }
+  // coarsest: sweeps 2..`sweeps` of damped Jacobi, ping-pong with the scratch
+  float* zfin;
+  {
+    const MgGeom& g = t->g[Lc];
+    const int ex = g.ext[s][0], ey = g.ext[s][1], ez = g.ext[s][2];
+    const int n = ex * ey * ez;
+    const float* rl = lds + base(Lc);
+    float* cur = lds + base(Lc) + n;
+    float* nxt = lds + base(Lc + 1);
+    const float4* op = t->op[Lc] + g.off[s];
+    int nb[kMgCoarsePer][6];
+    float w[kMgCoarsePer][6], dg[kMgCoarsePer], idg[kMgCoarsePer], rv[kMgCoarsePer];
+    for (int u = 0; u < kMgCoarsePer; ++u) {
+      const int i = tid + u * nth;
+      dg[u] = 1.f; idg[u] = 0.f; rv[u] = 0.f;
+      for (int e = 0; e < 6; ++e) { nb[u][e] = 0; w[u][e] = 0.f; }
+      if (i >= n) continue;
+      const int c3[3] = {i % ex, (i / ex) % ey, i / (ex * ey)};
+      const int e3[3] = {ex, ey, ez};
+      const float4 o = op[i];
+      const float wp[3] = {o.y, o.z, o.w};
+      dg[u] = o.x;
+      idg[u] = mg_rcp(o.x);
+      rv[u] = rl[i];
+      for (int d = 0; d < 3; ++d) {
+        const int stride = d == 0 ? 1 : (d == 1 ? ex : ex * ey);
+        nb[u][2 * d] = i; nb[u][2 * d + 1] = i;
+        if (c3[d] + 1 < e3[d]) { nb[u][2 * d] = i + stride; w[u][2 * d] = wp[d]; }
+        if (c3[d] >= 1) {
+          const float4 om = op[i - stride];
+          nb[u][2 * d + 1] = i - stride;
+          w[u][2 * d + 1] = d == 0 ? om.y : (d == 1 ? om.z : om.w);
+        }
+      }
+    }
+    for (int sw = 1; sw < sweeps; ++sw) {
+      for (int u = 0; u < kMgCoarsePer; ++u) {
+        const int i = tid + u * nth;
+        if (i >= n) continue;
+        float az = dg[u] * cur[i];
+        for (int e = 0; e < 6; ++e) az -= w[u][e] * cur[nb[u][e]];
+        nxt[i] = cur[i] + omega * (rv[u] - az) * idg[u];
+      }
+      __syncthreads();
+      float* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+    }
+    zfin = cur;
+  }
+  // up: z' = z_L + P z_{L+1} in place, then z'' = z' + omega (r_L - A_L z') / diag
+  double s0 = 0.0;
+  for (int L = Lc - 1; L >= L0; --L) {
+    const MgGeom& gf = t->g[L];
+    const int ex = gf.ext[s][0], ey = gf.ext[s][1], ez = gf.ext[s][2];
+    const int cx = t->g[L + 1].ext[s][0], cy = t->g[L + 1].ext[s][1];
+    const int n = ex * ey * ez;
+    const float* rl = lds + base(L);
+    float* zl = lds + base(L) + n;
+    for (int i = tid; i < n; i += nth) {
+      const int x = i % ex, y = (i / ex) % ey, z = i / (ex * ey);
+      zl[i] = zl[i] + zfin[((z >> 1) * cy + (y >> 1)) * cx + (x >> 1)];
+    }
+    __syncthreads();
+    float* out = lds + base(Lc + 1);
+    const float4* op = t->op[L] + gf.off[s];
+    for (int i0 = tid; i0 < n; i0 += kMgTailPer * nth) {
+      float4 o[kMgTailPer];
+      float wm[kMgTailPer][3];
+#pragma unroll
+      for (int u = 0; u < kMgTailPer; ++u) {
+        const int i = i0 + u * nth;
+        const int x = i % ex, y = (i / ex) % ey, z = i / (ex * ey);
+        const bool in = i < n;
+        o[u] = in ? op[i] : make_float4(1.f, 0.f, 0.f, 0.f);
+        wm[u][0] = in && x >= 1 ? op[i - 1].y : 0.f;
+        wm[u][1] = in && y >= 1 ? op[i - ex].z : 0.f;
+        wm[u][2] = in && z >= 1 ? op[i - ex * ey].w : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kMgTailPer; ++u) {
+        const int i = i0 + u * nth;
+        if (i < n) {
+          const int x = i % ex, y = (i / ex) % ey, z = i / (ex * ey);
+          const float4 oo = o[u];
+          const float zp = zl[i];
+          float od = 0.f;
+          if (x + 1 < ex) od -= oo.y * zl[i + 1];
+          if (y + 1 < ey) od -= oo.z * zl[i + ex];
+          if (z + 1 < ez) od -= oo.w * zl[i + ex * ey];
+          if (x >= 1) od -= wm[u][0] * zl[i - 1];
+          if (y >= 1) od -= wm[u][1] * zl[i - ex];
+          if (z >= 1) od -= wm[u][2] * zl[i - ex * ey];
+          const float rvi = rl[i];
+          const float v = zp + omega * (rvi - (oo.x * zp + od)) * mg_rcp(oo.x);
+          if (L > L0) {
+            out[i] = v;
+          } else {
+            zout[gf.off[s] + i] = v;
+            s0 += (double)(rvi * v);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    zfin = out;
+  }
+  if (partials) {
+    s0 = wave_sum(s0);
+    if ((tid & 63) == 0) red[tid >> 6] = s0;
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0;
+      for (int wv = 0; wv < (nth >> 6); ++wv) a += red[wv];
+      partials[2 * s] = a;
+      partials[2 * s + 1] = 0.0;
     }
   }
 }
