@@ -581,6 +581,54 @@ def net_kernels(args):
     print(json.dumps({"net_kernels": rows}), flush=True)
 
 
+def variant_sweep(args):
+    """--variant-sweep: the even-parity PCG with the Jacobi and with the
+    multigrid preconditioner on the validation problems and on fBm / nebula
+    media of several sizes and orders (best of 3 solves after a warm-up each);
+    writes the table (default profiles/variant_sweep.md), the measurement
+    behind AUTO's choice."""
+    import torch
+    from synth import config_checkerboard, config_point_source, config_p3_fbm, config_p5_nebula
+    from paper_1807_00410_amd.solver import Solver
+    dev = torch.device("cuda:0")
+    cases = [("checkerboard 71 x 71 P%d" % o, config_checkerboard(o, n=71), 1e-10) for o in range(1, 6)]
+    cases += [("point source 80^3 P%d" % o, config_point_source(o, n=80), 1e-10) for o in range(1, 6)]
+    for n in (24, 32, 48):
+        cases += [("P3 fBm %d^3" % n, config_p3_fbm(n=n), 1e-8), ("P5 nebula %d^3" % n, config_p5_nebula(n=n), 1e-8)]
+    for n in (24, 32, 48):
+        cases += [("P2 fBm %d^3" % n, config_p3_fbm(n=n, order=2), 1e-8),
+                  ("P4 fBm %d^3" % n, config_p3_fbm(n=n, order=4), 1e-8)]
+    cases += [("P4 nebula 64^3", config_p5_nebula(n=64, order=4), 1e-8),
+              ("P6 nebula 64^3", config_p5_nebula(n=64, order=6), 1e-8)]
+    lines = ["# Jacobi vs multigrid preconditioner of the even-parity PCG", "",
+             "Command (repository root, one GPU): `python3 bench.py --variant-sweep`", "",
+             "Each problem solved from u = 0 with `variant=\"schur\"` (Jacobi) and `variant=\"schur_mg\"`; best of 3",
+             "timed solves after one warm-up each; tolerance 1e-10 for the validation problems, 1e-8 otherwise.",
+             "AUTO takes the multigrid form for odd orders with at least 2^17 even-band unknowns.", "",
+             "| problem | even-band unknowns | Jacobi ms | Jacobi iterations | multigrid ms | multigrid iterations "
+             "| multigrid / Jacobi time | AUTO |", "|---|---|---|---|---|---|---|---|"]
+    for name, m, tol in cases:
+        s = Solver(m.order, m.dims, torch.as_tensor(m.sigma_t).to(dev), torch.as_tensor(m.albedo).to(dev),
+                   g=m.g, sigma_t_min=m.sigma_t_min, bc=m.bc, h=m.h)
+        rhs = s.rhs_from_q00(torch.as_tensor(m.q00[0]).to(dev))
+        res = {}
+        for v in ("schur", "schur_mg"):
+            x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+            best, info = min((timed_solve(s, rhs, x, warmup=1 if k == 0 else 0, tol=tol, variant=v) for k in range(3)),
+                             key=lambda r: r[0])
+            res[v] = (best, info["inner_iters"])
+        ne = s.even_unknowns()
+        auto = "multigrid" if (m.order % 2 == 1 and ne >= 1 << 17) else "Jacobi"
+        s.close()
+        lines.append("| %s | %d | %.2f | %d | %.2f | %d | %.2f | %s |" % (
+            name, ne, res["schur"][0] * 1e3, res["schur"][1], res["schur_mg"][0] * 1e3, res["schur_mg"][1],
+            res["schur_mg"][0] / res["schur"][0], auto))
+        print(lines[-1], file=sys.stderr, flush=True)
+    os.makedirs(os.path.dirname(os.path.abspath(args.sweep_out)), exist_ok=True)
+    with open(args.sweep_out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def profile_solve(args):
     """Profiling mode for rocprofv3 (--profile-solve): the headline workload
     (P5 nebula) solved by the default solver once untimed, then
@@ -679,6 +727,10 @@ def main():
     ap.add_argument("--accuracy", action="store_true",
                     help="compare the P5 128^3 solutions with the oracle's reference solutions in refdata/")
     ap.add_argument("--profile-zchunk", type=int, default=2)
+    ap.add_argument("--variant-sweep", action="store_true",
+                    help="Jacobi vs multigrid preconditioner over problem sizes and orders "
+                         "(writes the table to --sweep-out)")
+    ap.add_argument("--sweep-out", default=os.path.join(ROOT, "profiles", "variant_sweep.md"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)"
@@ -689,6 +741,9 @@ def main():
         return
     if args.profile_solve:
         profile_solve(args)
+        return
+    if args.variant_sweep:
+        variant_sweep(args)
         return
     if args.counters_summary:
         counters_summary(args)

@@ -161,7 +161,7 @@ typedef struct {
  * kernels: no extra memory traffic); the inner stop then tests the W-weighted
  * residual.  Needs the register-window stencil (PN_ERR_ARG with pn_set_tiles
  * or PN_FP64).  AUTO: on the register-window stencil SCHUR_MG for odd orders
- * with at least 2^18 even-band unknowns, SCHUR otherwise (CG_EQ when an axis
+ * with at least 2^17 even-band unknowns, SCHUR otherwise (CG_EQ when an axis
  * is Neumann or some cell has zero extinction); CG on the LDS-tiled one; the
  * batched solve treats AUTO as CG_EQ.  The FP64 refinement checks the true, unweighted residual
  * ||Q - A x|| in every case. */

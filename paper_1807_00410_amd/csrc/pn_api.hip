@@ -1019,10 +1019,10 @@ static bool mg_ok(const pn_ctx* c) { return schur_ok(c) && c->even.nk >= 1 && c-
 
 // AUTO's choice of the multigrid form: odd orders (with even N the top band
 // stays in the even set and the per-coefficient blocks miss its coupling to
-// l = N - 2: 1.65x fewer iterations against Jacobi, not enough for the V-cycle's
-// cost) with at least 2^18 even-band unknowns (below that its ten small
-// launches per iteration cost more than the iterations they save).
-constexpr long long kMgAutoMinEven = 1LL << 18;
+// l = N - 2: 1.0-1.7x fewer iterations against Jacobi, not enough for the
+// V-cycle's cost) with at least 2^17 even-band unknowns (below that its
+// launches cost more per iteration than the iterations they save).
+constexpr long long kMgAutoMinEven = 1LL << 17;
 static bool mg_auto(const pn_ctx* c) {
   long long ne = 0;
   for (int s = 0; s < c->even.nk; ++s) {

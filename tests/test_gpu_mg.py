@@ -8,7 +8,7 @@ meet the FP64 residual measured by the oracle's assembled matrix and lie
 within 1e-5 (rel-L2) of SuperLU -- orders 1..7, ragged, odd and degenerate
 grids (one level or several), heterogeneous media; it must take fewer
 iterations than the Jacobi-preconditioned form on heterogeneous media; AUTO
-equals it bitwise for odd orders with at least 2^18 even-band unknowns and
+equals it bitwise for odd orders with at least 2^17 even-band unknowns and
 the Jacobi form otherwise; periodic and mixed axes (cut at the seam in the
 preconditioner only) solve to the same bar; the variant is refused with a
 Neumann axis and in FP64.
@@ -37,7 +37,7 @@ def dev(a, dtype=torch.float32):
 
 def auto_variant(s):
     """The inner solver AUTO picks on the register-window stencil."""
-    return "schur_mg" if (s.layout.order % 2 == 1 and s.even_unknowns() >= 1 << 18) else "schur"
+    return "schur_mg" if (s.layout.order % 2 == 1 and s.even_unknowns() >= 1 << 17) else "schur"
 
 
 def solver(m, bc=VAC):

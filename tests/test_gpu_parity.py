@@ -333,12 +333,12 @@ def test_solve_equilibrated_cg_variant(order, n, bc):
     i_plain = _solve_and_check(m, 1e-8, "fp32_ir", variant="cg")
     print("iterations: equilibrated %d, plain %d" % (i_eq["inner_iters"], i_plain["inner_iters"]))
     # AUTO is the even-parity Schur form on the register-window stencil, with
-    # the multigrid preconditioner for odd orders of at least 2^18 even-band
+    # the multigrid preconditioner for odd orders of at least 2^17 even-band
     # unknowns
     s = make_solver(m)
     rhs = s.rhs_from_q00(dev(m.q00[0]))
     xa, ia = s.solve(rhs, tol=1e-8)
-    big = s.layout.order % 2 == 1 and s.even_unknowns() >= 1 << 18
+    big = s.layout.order % 2 == 1 and s.even_unknowns() >= 1 << 17
     xe, ie = s.solve(rhs, tol=1e-8, variant="schur_mg" if big else "schur")
     assert ia["inner_iters"] == ie["inner_iters"] and torch.equal(xa, xe)
     s.close()
