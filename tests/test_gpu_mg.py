@@ -197,9 +197,9 @@ def test_apply_precond_definitions():
 # (order, dims, bc): level 1 is the coarsest (one-block coarsest kernel);
 # the one-launch tail from level 1; wide passes on level 1, tail from level 2;
 # wide passes on levels 1-2, tail from level 3; a periodic axis (cut at the
-# seam) with the tail from level 1
+# seam) with the tail from level 1; P7 (28 even coefficients, 28 tail blocks)
 REF_CASES = [(5, (9, 8, 7), VAC), (3, (20, 18, 16), VAC), (3, (24, 20, 22), VAC), (1, (48, 44, 40), VAC),
-             (3, (20, 18, 16), (VAC, PER, VAC))]
+             (3, (20, 18, 16), (VAC, PER, VAC)), (7, (12, 11, 13), VAC)]
 
 
 @pytest.mark.parametrize("order,dims,bc", REF_CASES)
@@ -220,7 +220,7 @@ def test_mg_preconditioner_vs_reference(order, dims, bc):
     err = float(np.linalg.norm(z - ref) / np.linalg.norm(ref))
     worst = float(np.abs(z - ref).max() / np.abs(ref).max())
     print("rel-L2 %.3g, largest difference %.3g of the largest entry" % (err, worst), flush=True)
-    # FP32 arithmetic through at most a dozen levels: measured 6e-8 - 1.1e-7
+    # FP32 arithmetic through at most a dozen levels: measured 6e-8 - 1.3e-7
     assert err <= 1e-6 and worst <= 1e-6
 
 
