@@ -244,3 +244,18 @@ def test_mg_preconditioner_symmetric_at_96():
     assert abs(uv - vu) <= 1e-5 * scale
     assert float(u.double() @ Bu) > 0 and float(v.double() @ Bv) > 0
     assert float((Buv - (Bu + 2.0 * Bv)).abs().max()) <= 1e-5 * float(Buv.abs().max())
+
+
+@pytest.mark.parametrize("dims,mg", [((28, 27, 27), False), ((28, 28, 27), True)])
+def test_auto_threshold(dims, mg):
+    # AUTO takes the multigrid form from 2^17 even-band unknowns on: P3 on
+    # 28 x 27 x 27 holds 127,036 of them, on 28 x 28 x 27 131,683
+    print("case auto-threshold dims=%s" % (dims,), flush=True)
+    m = config_small(3, dims, seed=71, sigma_range=(1.0, 40.0), albedo_range=(0.5, 0.99), sigma_t_min=1.0)
+    s = solver(m)
+    assert (s.even_unknowns() >= 1 << 17) == mg
+    rhs = s.rhs_from_q00(dev(m.q00[0]))
+    xa, ia = s.solve(rhs, tol=1e-8)
+    xv, iv = s.solve(rhs, tol=1e-8, variant="schur_mg" if mg else "schur")
+    s.close()
+    assert ia["status"] == 0 and ia["inner_iters"] == iv["inner_iters"] and torch.equal(xa, xv)
