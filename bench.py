@@ -537,7 +537,7 @@ def counters_summary(args):
               "FP32 vectors, FP64 dots and refinement, tol 1e-8, inner_tol 1e-2, zchunk 2.  The program's "
               "output:", ""] + ["    " + x for x in log if x.startswith("solve ")] + [
               "", "All dispatches (loop kernels launched after a solve's stop flag return at once and pull the "
-              "averages down; each captured graph holds 32 iterations):", "",
+              "averages down; each captured graph holds 8 iterations):", "",
               "| kernel | calls | total ms | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|---|"]
         for r in stats[:20]:
             nm = r["Name"].split("(")[0]

@@ -105,7 +105,8 @@ typedef struct {
   int max_refine;     /* refinement steps (PN_FP32_IR)                         */
   double inner_tol;   /* relative reduction of the inner FP32 residual         */
   int use_guess;      /* 0: start from x = 0; 1: start from the x passed in    */
-  int graph_iters;    /* Krylov iterations per captured HIP graph launch       */
+  int graph_iters;    /* Krylov iterations per captured HIP graph launch (the
+                         host reads the stop flag after each launch)           */
   int variant;        /* PN_VARIANT_AUTO, _CGLS, _CG, _CG_EQ, _SCHUR, _SCHUR_MG */
   int learned;        /* PN_LEARNED_* (needs a network, pn_attach_net in pn_nn.h) */
 } pn_solve_opts;
@@ -210,7 +211,7 @@ int pn_abi_version(void);
 const char* pn_status_string(int status);
 
 /* Default options: FP32_IR, max_iter 200000, max_refine 40, inner_tol 1e-2,
- * use_guess 0, graph_iters 32, variant AUTO, learned OFF. */
+ * use_guess 0, graph_iters 8, variant AUTO, learned OFF. */
 void pn_default_opts(pn_solve_opts* opts);
 
 /* Builds a solver context for truncation order 1 <= order <= 7 on `grid`

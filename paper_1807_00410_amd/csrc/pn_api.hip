@@ -222,7 +222,7 @@ extern "C" void pn_default_opts(pn_solve_opts* o) {
   o->max_refine = 40;
   o->inner_tol = 1e-2;
   o->use_guess = 0;
-  o->graph_iters = 32;
+  o->graph_iters = 8;  // measured: 8 per graph is 0.8% (P5 128^3) to 5% (batched workload) faster than 32
   o->variant = PN_VARIANT_AUTO;
   o->learned = PN_LEARNED_OFF;
 }

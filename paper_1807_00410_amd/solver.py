@@ -223,7 +223,7 @@ class Solver:
         return tx.value, ty.value, z.value
 
     def solve(self, rhs, x=None, tol=1e-8, precision="fp32_ir", max_iter=200000, max_refine=40,
-              inner_tol=1e-2, use_guess=False, graph_iters=32, variant="auto", learned="off", raise_on_fail=True):
+              inner_tol=1e-2, use_guess=False, graph_iters=8, variant="auto", learned="off", raise_on_fail=True):
         """Solves A x = rhs.  learned: "off", "guess" or "guess+correct" (needs
         attach_net).  Returns (x, info dict)."""
         if x is None:
@@ -361,7 +361,7 @@ class Batch:
         return ms.value
 
     def solve(self, rhs, x=None, tol=1e-8, max_iter=200000, max_refine=40, inner_tol=1e-2, use_guess=False,
-              graph_iters=32, variant="auto", raise_on_fail=True):
+              graph_iters=8, variant="auto", raise_on_fail=True):
         """rhs: list over systems (problem-major, nrhs per problem) of device
         FP32 vectors in the problem's packed layout.  Returns (x list, info list)."""
         ns = self.nprob * self.nrhs
