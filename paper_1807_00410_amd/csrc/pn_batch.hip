@@ -26,7 +26,11 @@
 
 namespace {
 
-constexpr int kMgThreads = 4;  // host threads of the batched multigrid path (the GPU's hardware queues)
+// Host threads of the batched multigrid path (at most the host's hardware
+// threads): more than the GPU's hardware queues, since each thread waits on
+// the host for its problem's stop flag after every captured graph (48 x 8
+// systems: 4 threads 3.81 s, 8 threads 3.71 s, 16 threads 3.62 s).
+constexpr int kMgThreads = 16;
 
 struct Group {
   int order = 0, gen = 0;  // gen: some axis is not vacuum (general-boundary kernels)
@@ -476,7 +480,8 @@ extern "C" pn_status pn_batch_solve(pn_batch* b, const float* const* rhs, double
     // problems run concurrently on kMgThreads host threads (each problem has
     // its own solve stream and workspace); largest first to the least-loaded
     // thread.  Every system's arithmetic is independent of the schedule.
-    const int nth = std::max(1, std::min(kMgThreads, b->nprob));
+    const int hw = (int)std::thread::hardware_concurrency();
+    const int nth = std::max(1, std::min(std::min(kMgThreads, b->nprob), hw > 0 ? hw : kMgThreads));
     std::vector<int> order(b->nprob);
     for (int p = 0; p < b->nprob; ++p) order[p] = p;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c2) { return b->prob[a]->n > b->prob[c2]->n; });
